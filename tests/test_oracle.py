@@ -1,0 +1,278 @@
+"""The CPU oracle against closed forms, invariants, brute force and the
+paper's constants; plus planted mistakes that each pin must catch."""
+import types
+
+import numpy as np
+import pytest
+
+import oracle.core as oc
+import synth
+from tests import pins
+
+PINS = [
+    pins.check_filter_golden,
+    pins.check_filter_diagonal,
+    pins.check_filter_rotated,
+    pins.check_filter_unit_at_mu1,
+    pins.check_lanczos_bounds,
+    pins.check_lanczos_full_spectrum,
+    pins.check_condest_golden,
+    pins.check_qr_selection,
+    pins.check_shift_formula,
+    pins.check_caqr_orthogonality,
+    pins.check_caqr_fallback,
+    pins.check_rr_invariant_subspace,
+    pins.check_rr_interlacing,
+    pins.check_residual_bruteforce,
+    pins.check_eigval_grad,
+]
+
+
+@pytest.mark.parametrize("check", PINS, ids=lambda f: f.__name__)
+def test_pin(check):
+    check(oc)
+
+
+# ---------------------------------------------------------------- generators
+
+@pytest.mark.parametrize("basis", ["gaussian", "fourier"])
+def test_generator_spectrum(basis):
+    lam = synth.dft_like_spectrum(300)
+    A = synth.hermitian_from_spectrum(lam, basis=basis, seed=3)
+    assert np.array_equal(A, A.conj().T)
+    ev = np.linalg.eigvalsh(A)
+    assert np.max(np.abs(ev - lam)) <= 1e-13 * np.max(np.abs(lam))
+
+
+def test_dft_like_spectrum_shape():
+    lam = synth.dft_like_spectrum(20000)
+    assert lam.shape == (20000,)
+    assert np.all(np.diff(lam) > 0)
+    low = lam[:1000]
+    assert low.min() > -1.0 and low.max() < -0.8
+    assert lam[1000] > -0.8 and lam[-1] == 10.0
+
+
+def test_fourier_rotation_matches_dense_unitary():
+    """The FFT construction equals F diag(phi) F diag(lam) (F diag(phi) F)^H."""
+    N = 64
+    lam = np.linspace(-1, 2, N)
+    rng = np.random.default_rng(synth.problems.SEED_Q)
+    phi = np.exp(2j * np.pi * rng.random(N))
+    F = np.fft.fft(np.eye(N), axis=0, norm="ortho")
+    Q = F @ np.diag(phi) @ F
+    ref = (Q * lam) @ Q.conj().T
+    got = synth.hermitian_from_spectrum(lam, "fourier")
+    assert np.max(np.abs(got - 0.5 * (ref + ref.conj().T))) <= 1e-13
+
+
+# ---------------------------------------------------------------- whole solve
+
+def test_solve_bruteforce_small():
+    pins.check_solve_bruteforce(oc, N=120, nev=10, nex=6, seed=12)
+
+
+def test_solve_bruteforce_dft_like():
+    pins.check_solve_bruteforce(oc, N=200, nev=8, nex=4, seed=14,
+                                spectrum=synth.dft_like_spectrum(200))
+
+
+def test_parity_problem_known_spectrum(parity_problem, parity_oracle):
+    p, r = parity_problem, parity_oracle
+    assert r.converged
+    normA = p.norm2
+    assert np.max(np.abs(r.evals - p.lam[: p.nev])) <= 1e-10 * normA
+    X = r.evecs
+    resid = np.linalg.norm(p.A @ X - X * r.evals, axis=0)
+    assert np.max(resid) <= 1e-10 * normA
+    assert np.linalg.norm(X.conj().T @ X - np.eye(p.nev), 2) <= 1e-12
+    # reported residuals are the true ones
+    assert np.max(np.abs(resid - r.resid)) <= 1e-12
+
+
+def test_condest_bounds_computed_condition(parity_problem):
+    """The estimate bounds kappa_2 of the filtered block from above
+    (Sec. 4.2 reports this for every iteration after the first)."""
+    p = parity_problem
+    rec = []
+    orig = oc.caqr
+
+    def spy(X, cond, force=None):
+        s = np.linalg.svd(X, compute_uv=False)
+        rec.append((cond, s[0] / s[-1]))
+        return orig(X, cond, force)
+
+    try:
+        oc.caqr = spy
+        oc.chase(p.A, oc.Params(nev=p.nev, nex=p.nex), V0=p.V0, starts=p.starts)
+    finally:
+        oc.caqr = orig
+    assert len(rec) >= 2
+    for est, com in rec[1:]:
+        assert est >= com, (est, com)
+
+
+def test_householder_same_matvecs(parity_problem, parity_oracle):
+    """CholeskyQR and Householder QR give the same MatVecs and iteration
+    counts (Sec. 4.3, Table 2 discussion)."""
+    p = parity_problem
+    hh = oc.chase(p.A, oc.Params(nev=p.nev, nex=p.nex, force_qr=oc.QR_HOUSEHOLDER),
+                  V0=p.V0, starts=p.starts)
+    assert hh.iterations == parity_oracle.iterations
+    assert hh.filter_matvecs == parity_oracle.filter_matvecs
+    assert np.max(np.abs(hh.evals - parity_oracle.evals)) <= 1e-12
+
+
+def test_not_converged_status(parity_problem):
+    p = parity_problem
+    r = oc.chase(p.A, oc.Params(nev=p.nev, nex=p.nex, max_iter=1), V0=p.V0, starts=p.starts)
+    assert not r.converged and r.iterations == 1
+    assert r.evals.shape == (p.nev,) and np.all(np.diff(r.evals) >= 0)
+
+
+def test_invalid_arguments():
+    A = np.eye(10, dtype=np.complex128)
+    with pytest.raises(ValueError):
+        oc.chase(A, oc.Params(nev=8, nex=2))
+    with pytest.raises(ValueError):
+        oc.chase(A, oc.Params(nev=2, nex=2, deg=3))
+
+
+def test_degree_opt_properties():
+    resd = np.array([1e-2, 1e-6, 1e-11, np.inf, 1e-3])
+    Lam = np.array([-1.0, -0.9, -0.95, -0.5, 0.5])
+    d = oc.degree_opt(resd, Lam, c=0.5, e=0.9, tol_abs=1e-10, max_deg=36, deg_extra=2)
+    assert np.all(d % 2 == 0) and np.all(d >= 2) and np.all(d <= 36)
+    assert d[0] > d[1]            # larger residual, same region -> more steps
+    assert d[2] == 2              # already converged
+    assert d[3] == 36             # non-finite residual -> cap
+    assert d[4] == 36             # inside the damped interval -> cap
+
+
+def test_lock_order():
+    order, n = oc.lock_order(np.array([1.0, 1e-12, 1e-11, 1e-12, 1e-13]), 3, 1e-10)
+    assert n == 2 and list(order) == [1, 2, 0, 3, 4]
+
+
+# ---------------------------------------------------------------- planted mistakes
+
+def _mutant(**overrides):
+    m = types.ModuleType("oracle_mutant")
+    m.__dict__.update({k: v for k, v in oc.__dict__.items() if not k.startswith("__")})
+    m.__dict__.update(overrides)
+    # functions look globals up in their own module: rebind them to the mutant
+    for name, fn in list(m.__dict__.items()):
+        if isinstance(fn, types.FunctionType) and name not in overrides:
+            m.__dict__[name] = types.FunctionType(fn.__code__, m.__dict__, fn.__name__,
+                                                  fn.__defaults__, fn.__closure__)
+    return m
+
+
+def _coeffs_wrong_beta_sign(c, e, mu1, m):
+    return [(a, g, -b) for a, g, b in oc.filter_coefficients(c, e, mu1, m)]
+
+
+def _coeffs_no_shift(c, e, mu1, m):
+    return [(a, 0.0, b) for a, g, b in oc.filter_coefficients(c, e, mu1, m)]
+
+
+def _coeffs_unscaled_first(c, e, mu1, m):
+    out = oc.filter_coefficients(c, e, mu1, m)
+    out[0] = (2.0 * out[0][0], out[0][1], out[0][2])
+    return out
+
+
+def _filter_transposed(A, V, degs, c, e, mu1):
+    return oc.chebyshev_filter(A.T, V, degs, c, e, mu1)
+
+
+def _rr_no_conj(A, Q):
+    B = A @ Q
+    G = Q.T @ B
+    G = 0.5 * (G + G.conj().T)
+    theta, W = np.linalg.eigh(G)
+    return theta, Q @ W
+
+
+def _resid_dropped_theta(A, X, theta):
+    return np.linalg.norm(A @ X, axis=0)
+
+
+def _cond_swapped(Lam, c, e, degs, locked):
+    t_first = (Lam[0] - c) / e
+    t_active = (Lam[locked] - c) / e
+    d = int(degs[locked])
+    d_max = int(np.max(degs[locked:]))
+    return oc.rho(t_first) ** d * oc.rho(t_active) ** (d_max - d)
+
+
+def _shift_ten(m, n, fro2):
+    return 10.0 * (m * n + n * (n + 1)) * oc.U_ROUNDOFF * fro2
+
+
+def _select_swapped(cond):
+    if cond > oc.COND_SHIFTED:
+        return oc.QR_SHIFTED
+    if cond <= oc.COND_CHOLQR1:
+        return oc.QR_CHOLQR1
+    return oc.QR_CHOLQR2
+
+
+def _rsolve_wrong(X, R):
+    return X @ np.linalg.inv(R).T
+
+
+def _bsup_no_beta(A, starts, ne, k=25):
+    b, m1, mne, nrm = oc.lanczos_bounds(A, starts, ne, k)
+    top = max(oc.tridiagonal_eig(*oc.lanczos_run(A, starts[:, r], min(k, A.shape[0])))[0][-1]
+              for r in range(starts.shape[1]))
+    return top, m1, min(mne, top), nrm
+
+
+def _lanczos_missing_term(A, start, k):
+    v = start / np.linalg.norm(start)
+    alphas, betas = [], []
+    for _ in range(k):
+        w = A @ v
+        alpha = float(np.real(np.vdot(v, w)))
+        w = w - alpha * v
+        beta = float(np.linalg.norm(w))
+        alphas.append(alpha)
+        betas.append(beta)
+        v = w / beta
+    return np.array(alphas), np.array(betas)
+
+
+def _grad_transposed(X, g):
+    return (X.conj() * g[None, :]) @ X.T
+
+
+MUTANTS = [
+    ("beta sign", dict(filter_coefficients=_coeffs_wrong_beta_sign),
+     [pins.check_filter_golden, pins.check_filter_diagonal]),
+    ("no shift", dict(filter_coefficients=_coeffs_no_shift),
+     [pins.check_filter_diagonal, pins.check_filter_rotated]),
+    ("first step", dict(filter_coefficients=_coeffs_unscaled_first),
+     [pins.check_filter_golden, pins.check_filter_unit_at_mu1]),
+    ("transposed A", dict(chebyshev_filter=_filter_transposed), [pins.check_filter_rotated]),
+    ("RR without conj", dict(rayleigh_ritz=_rr_no_conj),
+     [pins.check_rr_invariant_subspace, pins.check_rr_interlacing]),
+    ("residual theta dropped", dict(residual_norms=_resid_dropped_theta),
+     [pins.check_residual_bruteforce, pins.check_rr_invariant_subspace]),
+    ("condest exponents swapped", dict(cond_est=_cond_swapped), [pins.check_condest_golden]),
+    ("shift factor", dict(shifted_shift=_shift_ten), [pins.check_shift_formula]),
+    ("threshold inclusive", dict(select_qr=_select_swapped), [pins.check_qr_selection]),
+    ("TRSM transposed", dict(_right_solve_upper=_rsolve_wrong), [pins.check_caqr_orthogonality]),
+    ("b_sup too low", dict(lanczos_bounds=_bsup_no_beta), [pins.check_lanczos_bounds]),
+    ("Lanczos three-term dropped", dict(lanczos_run=_lanczos_missing_term),
+     [pins.check_lanczos_full_spectrum]),
+    ("gradient transposed", dict(eigval_grad=_grad_transposed), [pins.check_eigval_grad]),
+]
+
+
+@pytest.mark.parametrize("name,overrides,checks", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(name, overrides, checks):
+    mutant = _mutant(**overrides)
+    for check in checks:
+        with pytest.raises(AssertionError):
+            check(mutant)
