@@ -1,0 +1,169 @@
+/*
+ * chase_hip.h -- C ABI of the MI355X (gfx950) ChASE hot path.
+ *
+ * ChASE finds the nev lowest eigenpairs of a dense Hermitian matrix H by
+ * Chebyshev-filtered subspace iteration (Wu & Di Napoli, arXiv 2309.15595):
+ * Lanczos spectral bounds, then a loop of {Chebyshev filter (Eq. 1),
+ * condition-number estimate (Alg. 5), 1D-CAQR (Alg. 3 and Alg. 4),
+ * Rayleigh-Ritz, residuals, deflation and locking, degree optimisation} as in
+ * Alg. 1 and Alg. 2, here on one GPU (a 1 x 1 grid: every AllReduce is the
+ * identity and B2 aliases C2).
+ *
+ * Conventions for every entry point:
+ *   - matrices are column-major complex128 ((re, im) double pairs), with a
+ *     leading dimension >= the row count, addressed by DEVICE pointers unless
+ *     an argument says (host);
+ *   - device pointers must be 16-byte aligned;
+ *   - sizes are int64_t;
+ *   - work is ordered on `stream` after the caller's earlier work on it; an
+ *     entry point returns once its results are complete on the device
+ *     (host-synchronous) unless it says otherwise;
+ *   - the caller owns every buffer it passes; the library never frees or
+ *     retains a caller pointer after returning.
+ *
+ * Return codes (LAPACK-like): 0 success; -k argument k invalid; 1 the solve
+ * stopped at max_iter before nev pairs converged (outputs hold the best
+ * approximations); 2 device allocation failed; 3 HIP runtime error (see
+ * chase_last_error); 4 numerical breakdown (non-finite values, or every QR
+ * route failed).
+ */
+#ifndef CHASE_HIP_H
+#define CHASE_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* chase_stream_t; /* a hipStream_t; NULL = the default stream */
+
+enum {
+  CHASE_FP64 = 0,      /* every step in FP64 */
+  CHASE_FP32_MIXED = 1 /* filter GEMMs in FP32 until a vector's residual reaches
+                          the FP32 floor, then FP64; QR, RR, residuals in FP64 */
+};
+
+enum {
+  CHASE_QR_AUTO = -1,  /* Alg. 4's choice from CondEst */
+  CHASE_QR_CHOLQR1 = 0,
+  CHASE_QR_CHOLQR2 = 1,
+  CHASE_QR_SHIFTED = 2,
+  CHASE_QR_HOUSEHOLDER = 3
+};
+
+/* Inputs of Alg. 2 (nev, nex, deg, tol, MaxIter, opt) plus the readings the
+ * paper leaves open.  Fill with chase_default_params first. */
+typedef struct {
+  int32_t nev;          /* wanted eigenpairs, >= 1 */
+  int32_t nex;          /* search-space increment, >= 0, nev + nex < N */
+  int32_t deg;          /* initial filter degree, even, >= 2 (20) */
+  int32_t max_deg;      /* cap on optimised degrees, even (36) */
+  int32_t deg_extra;    /* margin added by degree optimisation (2) */
+  int32_t max_iter;     /* MaxIter (25) */
+  int32_t opt;          /* 1 = per-vector degree optimisation (1) */
+  int32_t precision;    /* CHASE_FP64 or CHASE_FP32_MIXED */
+  int32_t lanczos_steps;/* steps per Lanczos run (25) */
+  int32_t force_qr;     /* CHASE_QR_AUTO, or force one QR variant (testing) */
+  int32_t bounds_given; /* 1 = skip Lanczos and use b_sup, mu_1, mu_ne, norm_est */
+  int32_t pad0;
+  double tol;           /* residual threshold relative to ||H|| (1e-10) */
+  double b_sup, mu_1, mu_ne, norm_est;
+  double mixed_switch;  /* FP32 -> FP64 switch at resd <= mixed_switch * ||H|| (1e-6) */
+  uint64_t seed;        /* generator of the initial block / Lanczos starts when
+                           the caller supplies none */
+} chase_params_t;
+
+typedef struct {
+  int32_t status;
+  int32_t iterations;
+  int32_t locked;
+  int32_t qr_count[4];      /* CholQR1, CholQR2, shifted CholQR2, Householder */
+  int32_t pad0;
+  int64_t filter_matvecs;   /* sum over iterations of sum_j d_j */
+  int64_t filter_matvecs_fp32; /* of which in FP32 (mixed precision) */
+  int64_t total_matvecs;    /* filter + Lanczos + Rayleigh-Ritz + residual */
+  int64_t filter_launches;  /* filter GEMM launches (one per degree step) */
+  double filter_flops;      /* 8 N^2 filter_matvecs */
+  double t_total, t_lanczos, t_filter, t_qr, t_rr, t_resid; /* seconds (HIP events) */
+  double bounds[4];         /* b_sup, mu_1, mu_ne, norm_est actually used */
+} chase_stats_t;
+
+typedef struct chase_handle_s* chase_handle_t;
+
+/* Defaults of the experiments (deg 20, max_deg 36, tol 1e-10, opt on). */
+int chase_default_params(chase_params_t* p);
+
+/* Allocates the device workspace for problems of order N with the given
+ * nev + nex: C2 and B (N x n_e each, Alg. 2's buffers; the caller's V is C),
+ * the n_e x n_e Rayleigh quotient A / Gram matrix, split-K partials, the
+ * Lanczos vectors and, for CHASE_FP32_MIXED, an FP32 copy of H (8 N^2 bytes)
+ * and two FP32 N x n_e blocks.  Memory model of Eq. (2) at p = q = 1.
+ * Returns 2 when an allocation fails (nothing is leaked). */
+int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h);
+
+/* Solves for the nev lowest eigenpairs of Hermitian H (Alg. 2).
+ *   A      (device) N x N, full Hermitian storage, read only
+ *   V      (device) N x (nev+nex), in/out.  On entry the initial block when
+ *          use_v0 = 1 (random or approximate eigenvectors, Sec. 1 / Sec. 3.1);
+ *          otherwise it is filled from params.seed.  On return columns
+ *          0..nev-1 hold the eigenvectors, ascending eigenvalues.
+ *   starts (device, nullable) N x nstarts Lanczos start vectors; NULL draws
+ *          4 from params.seed
+ *   ritzv, resid (host) nev doubles each: eigenvalues ascending, residual
+ *          norms ||H x - lambda x||_2
+ *   stats  (host, nullable) */
+int chase_solve(chase_handle_t h, const void* A, int64_t lda, void* V, int64_t ldv, int32_t use_v0,
+                const void* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
+                chase_stats_t* stats, chase_stream_t stream);
+
+int chase_destroy(chase_handle_t h);
+
+/* Gradient of L = sum_i g_i lambda_i with respect to H (Hellmann-Feynman:
+ * d lambda_i = x_i^H dH x_i):  G = X diag(g) X^H.
+ *   X (device) N x nev eigenvectors, g (device) nev doubles, G (device) N x N.
+ *   fill = 0 writes the full Hermitian G, 1 only its lower triangle.
+ * Asynchronous on `stream`. */
+int chase_eigval_grad(int64_t N, int32_t nev, const void* X, int64_t ldx, const double* g, void* G,
+                      int64_t ldg, int32_t fill, chase_stream_t stream);
+
+/* ---- steps of the loop, exposed for element-wise checks ------------------
+ * These run one step of Alg. 2 exactly as chase_solve does. */
+
+/* Chebyshev filter (Eq. 1, scaled three-term recurrence): column j of V
+ * (N x n) becomes p_{d_j}(H) v_j, p_m(x) = T_m((x-c)/e) / T_m((mu_1-c)/e).
+ * degs (host) n even degrees >= 2 sorted ascending; W (device) N x n
+ * scratch (the ping-pong partner).  Returns sum_j d_j in *matvecs (host). */
+int chase_filter(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int64_t ldw, int64_t N,
+                 int64_t n, const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs,
+                 chase_stream_t stream);
+
+/* 1D-CAQR (Alg. 4): V (N x n) is replaced by an orthonormal basis of its
+ * span with the variant chosen from cond (or forced, CHASE_QR_*).
+ * *variant (host) receives the variant that succeeded (after escalation
+ * CholQR1/2 -> shifted CholQR2 -> Householder). */
+int chase_caqr(void* V, int64_t ldv, int64_t N, int64_t n, double cond, int32_t force,
+               int32_t* variant, chase_stream_t stream);
+
+/* Rayleigh-Ritz (Alg. 2): Q (N x n, orthonormal) -> Ritz values theta
+ * (host, n, ascending) and Ritz vectors written over Q; resid (host, n)
+ * receives ||H x_j - theta_j x_j||. */
+int chase_rayleigh_ritz(const void* A, int64_t lda, void* Q, int64_t ldq, int64_t N, int64_t n,
+                        double* theta, double* resid, chase_stream_t stream);
+
+/* Lanczos bounds (reading of Alg. 1's first line): (b_sup, mu_1, mu_ne,
+ * norm_est) into out[4] (host) from nstarts runs of ksteps. */
+int chase_lanczos(const void* A, int64_t lda, int64_t N, const void* starts, int64_t ld_starts,
+                  int32_t nstarts, int32_t ksteps, int32_t ne, double* out, chase_stream_t stream);
+
+/* Alg. 5: condition-number estimate (host computation). */
+double chase_cond_est(const double* lam, double c, double e, const int32_t* degs, int32_t ne,
+                      int32_t locked);
+
+const char* chase_status_string(int status);
+const char* chase_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHASE_HIP_H */

@@ -1,0 +1,154 @@
+"""Python surface of the ChASE library: eigsh, an autograd eigenvalue op and
+column-major helpers.  PyTorch provides device memory and streams only;
+every step of the solve runs in libchase_hip.so.
+
+Layout.  The library is column-major.  A row-major torch tensor T viewed
+column-major is T^T, which for a Hermitian matrix is conj(T).  ``eigsh``
+therefore hands A's memory over untouched, solves conj(A) (same
+eigenvalues) and conjugates the returned vectors; no N^2 transpose is made.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_PRECISIONS = {"fp64": _lib.CHASE_FP64, "fp32": _lib.CHASE_FP32_MIXED,
+               "mixed": _lib.CHASE_FP32_MIXED}
+
+
+def colmajor(x, device="cuda") -> torch.Tensor:
+    """(rows x cols) array -> device tensor of shape (cols, rows) whose memory
+    is the column-major layout of x (leading dimension = rows)."""
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    return x.transpose(-2, -1).contiguous().to(device)
+
+
+def from_colmajor(t: torch.Tensor) -> np.ndarray:
+    """Inverse of colmajor: (cols, rows) device tensor -> numpy (rows x cols)."""
+    return t.detach().cpu().numpy().T.copy()
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    converged: bool
+    status: int
+    stats: dict
+
+
+class Solver:
+    """A chase_create/chase_destroy handle for problems of order N."""
+
+    def __init__(self, N: int, nev: int, nex: int, **params):
+        self.N, self.nev, self.nex = N, nev, nex
+        self.params = _lib.default_params(nev=nev, nex=nex, **params)
+        self.h = _lib.chase_create(N, self.params)
+
+    def close(self):
+        if self.h is not None:
+            _lib.chase_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve_colmajor(self, A_cm: torch.Tensor, V_cm: torch.Tensor, use_v0: bool = True,
+                       starts_cm: Optional[torch.Tensor] = None, stream=None):
+        """A_cm: (N, N) tensor holding A column-major; V_cm: (n_e, N) tensor
+        holding the N x n_e block column-major (in/out)."""
+        N = self.N
+        _check_dev(A_cm, (N, N))
+        _check_dev(V_cm, (self.nev + self.nex, N))
+        ns = 0 if starts_cm is None else starts_cm.shape[0]
+        if starts_cm is not None:
+            _check_dev(starts_cm, (ns, N))
+        ritz, resid, stats = _lib.chase_solve(
+            self.h, _lib.dptr(A_cm), N, _lib.dptr(V_cm), N, int(use_v0), _lib.dptr(starts_cm),
+            N, ns, self.nev, _lib.stream_ptr(stream))
+        return np.array(ritz), np.array(resid), SolveInfo(stats.status == 0, stats.status,
+                                                          stats.as_dict())
+
+
+def _check_dev(t: torch.Tensor, shape):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"expected complex128, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous tensor of shape {shape}, got {tuple(t.shape)}")
+
+
+def eigsh(A: torch.Tensor, nev: int, nex: int, *, deg: int = 20, tol: float = 1e-10,
+          opt: bool = True, max_deg: int = 36, max_iter: int = 25, V0=None, starts=None,
+          precision: str = "fp64", seed: int = 2309, return_raw: bool = False):
+    """nev lowest eigenpairs of the Hermitian (N, N) complex128 CUDA tensor A.
+
+    Returns (evals (nev,) float64 tensor, evecs (N, nev) complex128 tensor,
+    SolveInfo).  V0 (N, nev+nex) optional initial block, starts (N, r)
+    optional Lanczos start vectors.
+    """
+    N = A.shape[0]
+    ne = nev + nex
+    _check_dev(A, (N, N))
+    with Solver(N, nev, nex, deg=deg, tol=tol, opt=int(opt), max_deg=max_deg,
+                max_iter=max_iter, precision=_PRECISIONS[precision], seed=seed) as s:
+        # A's memory read column-major is conj(A): start from conj(V0) to stay
+        # on the same iterates, conjugate the eigenvectors back at the end.
+        if V0 is not None:
+            Vt = V0.conj().transpose(0, 1).contiguous()
+        else:
+            Vt = torch.empty((ne, N), dtype=torch.complex128, device=A.device)
+        st = None if starts is None else starts.conj().transpose(0, 1).contiguous()
+        ritz, resid, info = s.solve_colmajor(A, Vt, use_v0=V0 is not None, starts_cm=st)
+    evals = torch.from_numpy(ritz).to(A.device)
+    evecs = Vt[:nev].transpose(0, 1).conj()
+    info.stats["resid"] = resid
+    if return_raw:
+        return evals, evecs, info, Vt
+    return evals, evecs, info
+
+
+class ChaseEigvals(torch.autograd.Function):
+    """Lowest nev eigenvalues of Hermitian A with dL/dA = X diag(g) X^H
+    (Hellmann-Feynman); the backward recomputes nothing from the filter."""
+
+    @staticmethod
+    def forward(ctx, A, nev, nex, kwargs):
+        evals, _, info, Vt = eigsh(A, nev, nex, return_raw=True, **(kwargs or {}))
+        if not info.converged:
+            raise RuntimeError(f"ChASE did not converge (status {info.status})")
+        ctx.save_for_backward(Vt)
+        ctx.nev = nev
+        ctx.N = A.shape[0]
+        return evals
+
+    @staticmethod
+    def backward(ctx, g):
+        (Vt,) = ctx.saved_tensors
+        N, nev = ctx.N, ctx.nev
+        g = g.to(torch.float64).contiguous()
+        G = torch.empty((N, N), dtype=torch.complex128, device=Vt.device)
+        # Vt holds conj(X) column-major; the column-major product
+        # conj(X) diag(g) X^T read row-major is X diag(g) X^H.
+        _lib.chase_eigval_grad(N, nev, _lib.dptr(Vt), N, _lib.dptr(g), _lib.dptr(G), N, 0,
+                               _lib.stream_ptr())
+        return G, None, None, None
+
+
+def eigvalsh_lowest(A: torch.Tensor, nev: int, nex: int, **kwargs) -> torch.Tensor:
+    """Differentiable lowest-nev eigenvalues (see ChaseEigvals)."""
+    return ChaseEigvals.apply(A, nev, nex, kwargs)

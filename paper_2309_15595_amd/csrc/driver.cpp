@@ -1,0 +1,1070 @@
+// Host driver of the ChASE hot path on one MI355X: the loop of Alg. 2 with a
+// 1 x 1 grid (AllReduce = identity, B2 = C2), host scalar logic (bounds,
+// degree optimisation, CondEst, locking decisions) and the C ABI.
+//
+// Device work all runs in the hand-written kernels of zgemm.hip, cgemm.hip
+// and small.hip, except the n_e x n_e Hermitian eigensolve of Rayleigh-Ritz
+// (rocSOLVER zheevd) and the rarely taken Householder-QR fallback of Alg. 4
+// (rocSOLVER zgeqrf/zungqr).
+#include "../../include/chase_hip.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace chase {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const char* where, hipError_t err) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(err);
+}
+const char* last_error() { return g_last_error.c_str(); }
+
+static void set_msg(const std::string& s) { g_last_error = s; }
+
+// ---------------------------------------------------------------------------
+// Host scalar logic (shared by the solve and the step entry points)
+// ---------------------------------------------------------------------------
+
+// rho(t) = max(|t - sqrt(t^2-1)|, |t + sqrt(t^2-1)|), complex square root.
+static double rho_of(double t) {
+  std::complex<double> s = std::sqrt(std::complex<double>(t * t - 1.0, 0.0));
+  return std::max(std::abs(t - s), std::abs(t + s));
+}
+
+// Alg. 5.
+static double cond_est(const double* Lam, double c, double e, const int32_t* degs, int ne, int locked) {
+  const double t_first = (Lam[0] - c) / e;
+  const double t_active = (Lam[locked] - c) / e;
+  const int d = degs[locked];
+  int d_max = d;
+  for (int j = locked; j < ne; ++j) d_max = std::max(d_max, (int)degs[j]);
+  return std::pow(rho_of(t_active), d) * std::pow(rho_of(t_first), d_max - d);
+}
+
+// Alg. 4's branch.
+static int select_qr(double cond) {
+  if (cond > 1e8) return CHASE_QR_SHIFTED;
+  if (cond < 20.0) return CHASE_QR_CHOLQR1;
+  return CHASE_QR_CHOLQR2;
+}
+
+// Degree optimisation: steps needed for resd to fall to tol_abs at the
+// Chebyshev growth rate rho((lambda - c)/e), plus a margin; capped, even.
+static int degree_opt(double resd, double lam, double c, double e, double tol_abs, int max_deg, int extra) {
+  const double r = rho_of((lam - c) / e);
+  int d;
+  if (r <= 1.0 + 1e-12 || !std::isfinite(resd)) {
+    d = max_deg;
+  } else {
+    const double ratio = resd / tol_abs;
+    if (ratio <= 1.0) d = extra;
+    else d = (int)std::ceil(std::log(ratio) / std::log(r)) + extra;
+  }
+  d = std::min(std::max(d, 2), max_deg);
+  return d + (d % 2);
+}
+
+// Eigenpairs of a small real symmetric matrix by cyclic Jacobi rotations
+// (k <= a few dozen: the Lanczos tridiagonals).  Ascending eigenvalues;
+// Z column-major, column i the eigenvector of w[i].
+static void jacobi_eig(int k, std::vector<double> a, std::vector<double>& w, std::vector<double>& Z) {
+  Z.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) Z[i + (size_t)i * k] = 1.0;
+  auto A = [&](int i, int j) -> double& { return a[i + (size_t)j * k]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i < k; ++i) {
+        tot += A(i, j) * A(i, j);
+        if (i != j) off += A(i, j) * A(i, j);
+      }
+    if (off <= 1e-34 * tot || off == 0.0) break;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A(p, q);
+        if (apq == 0.0) continue;
+        const double theta = (A(q, q) - A(p, p)) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int r = 0; r < k; ++r) {  // columns p, q
+          const double arp = A(r, p), arq = A(r, q);
+          A(r, p) = cs * arp - sn * arq;
+          A(r, q) = sn * arp + cs * arq;
+        }
+        for (int r = 0; r < k; ++r) {  // rows p, q
+          const double apr = A(p, r), aqr = A(q, r);
+          A(p, r) = cs * apr - sn * aqr;
+          A(q, r) = sn * apr + cs * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double zrp = Z[r + (size_t)p * k], zrq = Z[r + (size_t)q * k];
+          Z[r + (size_t)p * k] = cs * zrp - sn * zrq;
+          Z[r + (size_t)q * k] = sn * zrp + cs * zrq;
+        }
+      }
+  }
+  std::vector<int> idx(k);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return A(x, x) < A(y, y); });
+  w.resize(k);
+  std::vector<double> Zs((size_t)k * k);
+  for (int i = 0; i < k; ++i) {
+    w[i] = A(idx[i], idx[i]);
+    for (int r = 0; r < k; ++r) Zs[r + (size_t)i * k] = Z[r + (size_t)idx[i] * k];
+  }
+  Z.swap(Zs);
+}
+
+// Spectral bounds from the Lanczos coefficients of `runs` runs (each
+// alpha/beta row of length ksteps, truncated at the first zero beta).
+static void bounds_from_lanczos(const std::vector<double>& alpha, const std::vector<double>& beta, int runs,
+                                int ksteps, int64_t N, int ne, double out[4]) {
+  double b_sup = -std::numeric_limits<double>::infinity();
+  double mu_1 = std::numeric_limits<double>::infinity();
+  double theta_max = -std::numeric_limits<double>::infinity();
+  std::vector<double> nodes, weights;
+  for (int r = 0; r < runs; ++r) {
+    int k = 0;
+    while (k < ksteps) {
+      ++k;
+      if (beta[(size_t)r * ksteps + k - 1] == 0.0) break;
+    }
+    std::vector<double> T((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) {
+      T[i + (size_t)i * k] = alpha[(size_t)r * ksteps + i];
+      if (i + 1 < k) {
+        T[i + (size_t)(i + 1) * k] = beta[(size_t)r * ksteps + i];
+        T[(i + 1) + (size_t)i * k] = beta[(size_t)r * ksteps + i];
+      }
+    }
+    std::vector<double> w, Z;
+    jacobi_eig(k, T, w, Z);
+    b_sup = std::max(b_sup, w[k - 1] + beta[(size_t)r * ksteps + k - 1]);
+    mu_1 = std::min(mu_1, w[0]);
+    theta_max = std::max(theta_max, w[k - 1]);
+    for (int i = 0; i < k; ++i) {
+      nodes.push_back(w[i]);
+      weights.push_back(Z[0 + (size_t)i * k] * Z[0 + (size_t)i * k]);
+    }
+  }
+  std::vector<int> order(nodes.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nodes[x] < nodes[y]; });
+  double cum = 0.0;
+  size_t idx = order.size() - 1;
+  for (size_t i = 0; i < order.size(); ++i) {
+    cum += weights[order[i]];
+    if ((double)N * cum / runs >= (double)ne) {
+      idx = i;
+      break;
+    }
+  }
+  double mu_ne = nodes[order[idx]];
+  mu_ne = std::min(std::max(mu_ne, mu_1), std::nextafter(b_sup, -std::numeric_limits<double>::infinity()));
+  out[0] = b_sup;
+  out[1] = mu_1;
+  out[2] = mu_ne;
+  out[3] = std::max(std::fabs(mu_1), std::fabs(theta_max));
+}
+
+// ---------------------------------------------------------------------------
+// Device workspace
+// ---------------------------------------------------------------------------
+
+struct Workspace {
+  int64_t N = 0;
+  int ne = 0;
+  int max_splits = 16;
+  z64* C2 = nullptr;     // N x ne
+  z64* B = nullptr;      // N x ne
+  z64* G = nullptr;      // ne x ne (Gram / Rayleigh quotient / eigenvectors)
+  z64* L = nullptr;      // ne x ne (Cholesky factor, then its inverse)
+  z64* T = nullptr;      // ne x ne scratch
+  z64* ws = nullptr;     // split-K partials
+  z64* tau = nullptr;    // Householder scalars (ne)
+  double* theta = nullptr;
+  double* resd = nullptr;
+  double* E = nullptr;   // heevd off-diagonal workspace
+  double* shift = nullptr;
+  int* info = nullptr;
+  int* flag = nullptr;
+  int* perm = nullptr;
+  z64* lzV = nullptr;    // Lanczos: N x 8 each
+  z64* lzVold = nullptr;
+  z64* lzW = nullptr;
+  z64* starts = nullptr; // N x 4 generated starts
+  double* lz_alpha = nullptr;
+  double* lz_beta = nullptr;
+  // mixed precision
+  c32* A32 = nullptr;
+  c32* X32a = nullptr;
+  c32* X32b = nullptr;
+  rocblas_handle rb = nullptr;
+  std::vector<void*> owned;
+
+  template <class T>
+  int alloc(T** p, size_t count) {
+    void* q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      set_msg("hipMalloc failed");
+      return kAllocFailed;
+    }
+    owned.push_back(q);
+    *p = reinterpret_cast<T*>(q);
+    return kOk;
+  }
+
+  int create(int64_t N_, int ne_, bool mixed, bool lanczos) {
+    N = N_;
+    ne = ne_;
+    const size_t nne = (size_t)N * ne, sq = (size_t)ne * ne;
+    int st = kOk;
+    st = st ? st : alloc(&C2, nne);
+    st = st ? st : alloc(&B, nne);
+    st = st ? st : alloc(&G, sq);
+    st = st ? st : alloc(&L, sq);
+    st = st ? st : alloc(&T, sq);
+    st = st ? st : alloc(&ws, (size_t)zgemm_splitk_workspace(ne, ne, max_splits));
+    st = st ? st : alloc(&tau, (size_t)ne);
+    st = st ? st : alloc(&theta, (size_t)ne);
+    st = st ? st : alloc(&resd, (size_t)ne);
+    st = st ? st : alloc(&E, (size_t)ne);
+    st = st ? st : alloc(&shift, 1);
+    st = st ? st : alloc(&info, 1);
+    st = st ? st : alloc(&flag, 1);
+    st = st ? st : alloc(&perm, (size_t)ne);
+    st = st ? st : alloc(&lz_alpha, 8 * 256);
+    st = st ? st : alloc(&lz_beta, 8 * 256);
+    if (lanczos) {
+      st = st ? st : alloc(&lzV, (size_t)N * 8);
+      st = st ? st : alloc(&lzVold, (size_t)N * 8);
+      st = st ? st : alloc(&lzW, (size_t)N * 8);
+      st = st ? st : alloc(&starts, (size_t)N * 4);
+    }
+    if (mixed) {
+      st = st ? st : alloc(&A32, (size_t)N * N);
+      st = st ? st : alloc(&X32a, nne);
+      st = st ? st : alloc(&X32b, nne);
+    }
+    if (!st && rocblas_create_handle(&rb) != rocblas_status_success) {
+      set_msg("rocblas_create_handle failed");
+      st = kHipError;
+    }
+    if (st) release();
+    return st;
+  }
+
+  void release() {
+    for (void* p : owned) (void)hipFree(p);
+    owned.clear();
+    if (rb) rocblas_destroy_handle(rb);
+    rb = nullptr;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Steps
+// ---------------------------------------------------------------------------
+
+// Filter (Eq. 1 with the scaled Chebyshev coefficients).  V: N x n in place
+// (the final iterate of an even degree lands back in V), W: ping-pong.
+// degs ascending.  Returns the number of GEMM launches in *launches.
+static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N,
+                      int64_t n, const int32_t* degs, double c, double e, double mu1, int64_t* matvecs,
+                      int64_t* launches, hipStream_t s) {
+  if (n <= 0) return kOk;
+  const int dmax = degs[n - 1];
+  int64_t mv = 0, nl = 0;
+  const double sigma1 = e / (mu1 - c);
+  double sigma = sigma1;
+  for (int k = 0; k < dmax; ++k) {  // computes X_{k+1}
+    int64_t s0 = 0;
+    while (s0 < n && degs[s0] < k + 1) ++s0;
+    const int64_t cols = n - s0;
+    if (cols <= 0) break;
+    double alpha, beta;
+    if (k == 0) {
+      alpha = sigma1 / e;
+      beta = 0.0;
+    } else {
+      const double sigma_next = 1.0 / (2.0 / sigma1 - sigma);
+      alpha = 2.0 * sigma_next / e;
+      beta = -sigma * sigma_next;
+      sigma = sigma_next;
+    }
+    // X_k lives in V for even k, in W for odd k; X_{k+1} overwrites X_{k-1}.
+    const bool cur_in_v = (k % 2 == 0);
+    const z64* cur = cur_in_v ? V : W;
+    const int64_t ldc = cur_in_v ? ldv : ldw;
+    z64* out = cur_in_v ? W : V;
+    const int64_t ldo = cur_in_v ? ldw : ldv;
+    GemmArgs g;
+    g.M = N; g.N = cols; g.K = N;
+    g.A = A; g.lda = lda;
+    g.B = cur + s0 * ldc; g.ldb = ldc;
+    g.Y = out + s0 * ldo; g.ldy = ldo;
+    g.Z = cur + s0 * ldc; g.ldz = ldc;
+    g.alpha = alpha; g.beta = beta; g.gamma = -alpha * c;
+    int st = zgemm_launch(0, 0, g, s, true);
+    if (st) return st;
+    mv += cols;
+    ++nl;
+  }
+  if (matvecs) *matvecs = mv;
+  if (launches) *launches = nl;
+  return kOk;
+}
+
+// FP32 filter for the columns still in low precision (same recurrence and
+// scalars as run_filter, complex64 data, FP32 accumulation on MFMA).
+static int run_filter_fp32(const c32* A32, int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int64_t n,
+                           const int32_t* degs, double c, double e, double mu1, int64_t* matvecs,
+                           int64_t* launches, hipStream_t s) {
+  if (n <= 0) return kOk;
+  int st = convert_z_to_c(V, ldv, X0, N, N, n, s);
+  if (st) return st;
+  const int dmax = degs[n - 1];
+  int64_t mv = 0, nl = 0;
+  const double sigma1 = e / (mu1 - c);
+  double sigma = sigma1;
+  int64_t done = 0;  // columns [0, done) already converted back
+  for (int k = 0; k < dmax; ++k) {
+    int64_t s0 = 0;
+    while (s0 < n && degs[s0] < k + 1) ++s0;
+    // columns that finished after step k (degree == k) are in X0 (k even): convert back
+    if (s0 > done) {
+      st = convert_c_to_z(X0 + done * N, N, V + done * ldv, ldv, N, s0 - done, s);
+      if (st) return st;
+      done = s0;
+    }
+    const int64_t cols = n - s0;
+    if (cols <= 0) break;
+    double alpha, beta;
+    if (k == 0) {
+      alpha = sigma1 / e;
+      beta = 0.0;
+    } else {
+      const double sigma_next = 1.0 / (2.0 / sigma1 - sigma);
+      alpha = 2.0 * sigma_next / e;
+      beta = -sigma * sigma_next;
+      sigma = sigma_next;
+    }
+    const bool cur0 = (k % 2 == 0);
+    c32* cur = cur0 ? X0 : X1;
+    c32* out = cur0 ? X1 : X0;
+    CGemmArgs g;
+    g.M = N; g.N = cols; g.K = N;
+    g.A = A32; g.lda = N;
+    g.B = cur + s0 * N; g.ldb = N;
+    g.Y = out + s0 * N; g.ldy = N;
+    g.Z = cur + s0 * N; g.ldz = N;
+    g.alpha = (float)alpha; g.beta = (float)beta; g.gamma = (float)(-alpha * c);
+    st = cgemm_filter_launch(g, s);
+    if (st) return st;
+    mv += cols;
+    ++nl;
+  }
+  if (n > done) {
+    st = convert_c_to_z(X0 + done * N, N, V + done * ldv, ldv, N, n - done, s);
+    if (st) return st;
+  }
+  if (matvecs) *matvecs = mv;
+  if (launches) *launches = nl;
+  return kOk;
+}
+
+// Gram matrix G = X^H X (Hermitised), X: N x n.
+static int gram(Workspace& w, const z64* X, int64_t ldx, int64_t n, hipStream_t s) {
+  GemmArgs g;
+  g.M = n; g.N = n; g.K = w.N;
+  g.A = X; g.lda = ldx;
+  g.B = X; g.ldb = ldx;
+  g.Y = w.G; g.ldy = n;
+  const int splits = choose_splits(n, n, w.N, w.max_splits);
+  return zgemm_splitk(1, 0, g, w.ws, splits, 1, s);
+}
+
+// X <- X R^{-1} with R = L^H from G = L L^H.  Returns 1 in *failed when the
+// Cholesky factorisation breaks down (X untouched).
+static int chol_apply(Workspace& w, z64* X, int64_t ldx, int64_t n, bool shifted, int* failed,
+                      hipStream_t s) {
+  int st = kOk;
+  if (shifted) {
+    st = add_cholqr_shift(w.G, n, n, w.N, w.shift, s);
+    if (st) return st;
+  }
+  st = potrf_lower(w.G, n, n, w.info, nullptr, s);
+  if (st) return st;
+  int info = 0;
+  CHASE_CHK(hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s));
+  CHASE_CHK(hipStreamSynchronize(s));
+  if (info != 0) {
+    *failed = 1;
+    return kOk;
+  }
+  *failed = 0;
+  st = trtri_lower(w.G, n, w.L, n, n, w.T, s);
+  if (st) return st;
+  GemmArgs g;  // B = X L^{-H}
+  g.M = w.N; g.N = n; g.K = n;
+  g.A = X; g.lda = ldx;
+  g.B = w.L; g.ldb = n;
+  g.Y = w.B; g.ldy = w.N;
+  g.upper_b = 1;
+  st = zgemm_launch(0, 1, g, s);
+  if (st) return st;
+  return copy_columns(w.B, w.N, X, ldx, w.N, n, s);
+}
+
+static int cholqr_pass(Workspace& w, z64* X, int64_t ldx, int64_t n, bool shifted, int* failed,
+                       hipStream_t s) {
+  int st = gram(w, X, ldx, n, s);
+  if (st) return st;
+  return chol_apply(w, X, ldx, n, shifted, failed, s);
+}
+
+static int householder(Workspace& w, z64* X, int64_t ldx, int64_t n, hipStream_t s) {
+  rocblas_set_stream(w.rb, s);
+  rocblas_status r = rocsolver_zgeqrf(w.rb, (rocblas_int)w.N, (rocblas_int)n,
+                                      reinterpret_cast<rocblas_double_complex*>(X), (rocblas_int)ldx,
+                                      reinterpret_cast<rocblas_double_complex*>(w.tau));
+  if (r != rocblas_status_success) {
+    set_msg("rocsolver_zgeqrf failed");
+    return kHipError;
+  }
+  r = rocsolver_zungqr(w.rb, (rocblas_int)w.N, (rocblas_int)n, (rocblas_int)n,
+                       reinterpret_cast<rocblas_double_complex*>(X), (rocblas_int)ldx,
+                       reinterpret_cast<rocblas_double_complex*>(w.tau));
+  if (r != rocblas_status_success) {
+    set_msg("rocsolver_zungqr failed");
+    return kHipError;
+  }
+  return kOk;
+}
+
+// Alg. 4 with escalation on Cholesky failure.
+static int caqr(Workspace& w, z64* X, int64_t ldx, int64_t n, double cond, int force, int* variant,
+                hipStream_t s) {
+  int v = force >= 0 ? force : select_qr(cond);
+  int failed = 0, st = kOk;
+  while (true) {
+    if (v == CHASE_QR_CHOLQR1 || v == CHASE_QR_CHOLQR2) {
+      const int passes = v == CHASE_QR_CHOLQR1 ? 1 : 2;
+      for (int p = 0; p < passes; ++p) {
+        st = cholqr_pass(w, X, ldx, n, false, &failed, s);
+        if (st) return st;
+        if (failed) break;
+      }
+      if (!failed) break;
+      v = CHASE_QR_SHIFTED;
+      continue;
+    }
+    if (v == CHASE_QR_SHIFTED) {
+      st = cholqr_pass(w, X, ldx, n, true, &failed, s);
+      if (st) return st;
+      for (int p = 0; p < 2 && !failed; ++p) {
+        st = cholqr_pass(w, X, ldx, n, false, &failed, s);
+        if (st) return st;
+      }
+      if (!failed) break;
+      v = CHASE_QR_HOUSEHOLDER;
+      continue;
+    }
+    st = householder(w, X, ldx, n, s);
+    if (st) return st;
+    v = CHASE_QR_HOUSEHOLDER;
+    break;
+  }
+  *variant = v;
+  return kOk;
+}
+
+// Rayleigh-Ritz on the active block plus residuals.  Q (= C2_a on entry,
+// orthonormal, N x n) and V (= C_a): on return V holds the Ritz vectors, Q a
+// copy of them, theta/resd (device) the Ritz values and residual norms.
+// HC = H Q is computed once (Alg. 2's H C); the residual's H V is formed as
+// (H Q) W, the same product reassociated.
+static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_t ldq, z64* V, int64_t ldv,
+                         int64_t n, hipStream_t s) {
+  if (n <= 0) return kOk;
+  const int64_t N = w.N;
+  GemmArgs g;  // B = H Q
+  g.M = N; g.N = n; g.K = N;
+  g.A = A; g.lda = lda;
+  g.B = Q; g.ldb = ldq;
+  g.Y = w.B; g.ldy = N;
+  int st = zgemm_launch(0, 0, g, s);
+  if (st) return st;
+  GemmArgs q;  // G = Q^H B, Hermitised
+  q.M = n; q.N = n; q.K = N;
+  q.A = Q; q.lda = ldq;
+  q.B = w.B; q.ldb = N;
+  q.Y = w.G; q.ldy = n;
+  st = zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits), 1, s);
+  if (st) return st;
+  rocblas_set_stream(w.rb, s);
+  rocblas_status r = rocsolver_zheevd(w.rb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n,
+                                      reinterpret_cast<rocblas_double_complex*>(w.G), (rocblas_int)n, w.theta,
+                                      w.E, w.info);
+  if (r != rocblas_status_success) {
+    set_msg("rocsolver_zheevd failed");
+    return kHipError;
+  }
+  GemmArgs b;  // V = Q W
+  b.M = N; b.N = n; b.K = n;
+  b.A = Q; b.lda = ldq;
+  b.B = w.G; b.ldb = n;
+  b.Y = V; b.ldy = ldv;
+  st = zgemm_launch(0, 0, b, s);
+  if (st) return st;
+  GemmArgs hv;  // Q <- (H Q) W = H V
+  hv.M = N; hv.N = n; hv.K = n;
+  hv.A = w.B; hv.lda = N;
+  hv.B = w.G; hv.ldb = n;
+  hv.Y = Q; hv.ldy = ldq;
+  st = zgemm_launch(0, 0, hv, s);
+  if (st) return st;
+  st = residual_norms(Q, ldq, V, ldv, w.theta, N, n, w.resd, s);
+  if (st) return st;
+  return copy_columns(V, ldv, Q, ldq, N, n, s);
+}
+
+static int lanczos(Workspace& w, const z64* A, int64_t lda, const z64* starts, int64_t lds, int nstarts,
+                   int ksteps, int ne, double out[4], hipStream_t s) {
+  const int64_t N = w.N;
+  ksteps = (int)std::min<int64_t>(ksteps, N);
+  if (nstarts < 1 || nstarts > 8 || ksteps < 1 || ksteps > 256) return -1;
+  int st = lanczos_init(starts, lds, w.lzV, w.lzVold, N, nstarts, s);
+  if (st) return st;
+  for (int j = 0; j < ksteps; ++j) {
+    st = hemv_block(A, lda, w.lzV, N, w.lzW, N, N, nstarts, s);
+    if (st) return st;
+    st = lanczos_step(w.lzV, w.lzVold, w.lzW, N, nstarts, j, ksteps, w.lz_alpha, w.lz_beta, s);
+    if (st) return st;
+  }
+  std::vector<double> al((size_t)nstarts * ksteps), be((size_t)nstarts * ksteps);
+  CHASE_CHK(hipMemcpyAsync(al.data(), w.lz_alpha, al.size() * 8, hipMemcpyDeviceToHost, s));
+  CHASE_CHK(hipMemcpyAsync(be.data(), w.lz_beta, be.size() * 8, hipMemcpyDeviceToHost, s));
+  CHASE_CHK(hipStreamSynchronize(s));
+  for (double x : al)
+    if (!std::isfinite(x)) return kBreakdown;
+  bounds_from_lanczos(al, be, nstarts, ksteps, N, ne, out);
+  return kOk;
+}
+
+static int apply_perm(Workspace& w, z64* X, int64_t ldx, const std::vector<int>& perm, bool also_c2,
+                      int64_t c2_off, hipStream_t s) {
+  const int64_t n = (int64_t)perm.size();
+  if (n == 0) return kOk;
+  CHASE_CHK(hipMemcpyAsync(w.perm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  int st = gather_columns(X, ldx, w.B, w.N, w.perm, w.N, n, s);
+  if (st) return st;
+  st = copy_columns(w.B, w.N, X, ldx, w.N, n, s);
+  if (st) return st;
+  if (also_c2) st = copy_columns(w.B, w.N, w.C2 + c2_off * w.N, w.N, w.N, n, s);
+  // the host vector must outlive the async copy
+  CHASE_CHK(hipStreamSynchronize(s));
+  return st;
+}
+
+struct PhaseTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  double acc = 0.0;
+  bool pending = false;
+  int init() {
+    CHASE_CHK(hipEventCreate(&a));
+    CHASE_CHK(hipEventCreate(&b));
+    return kOk;
+  }
+  void start(hipStream_t s) { (void)hipEventRecord(a, s); }
+  void stop(hipStream_t s) {
+    (void)hipEventRecord(b, s);
+    pending = true;
+  }
+  void collect() {  // after a synchronisation point
+    if (!pending) return;
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) acc += ms * 1e-3;
+    pending = false;
+  }
+  void destroy() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+static bool valid_params(const chase_params_t* p) {
+  if (!p) return false;
+  if (p->nev < 1 || p->nex < 0) return false;
+  if (p->deg < 2 || p->deg % 2 || p->max_deg < 2 || p->max_deg % 2) return false;
+  if (!(p->tol > 0)) return false;
+  if (p->max_iter < 1 || p->lanczos_steps < 1 || p->lanczos_steps > 256) return false;
+  if (p->precision != CHASE_FP64 && p->precision != CHASE_FP32_MIXED) return false;
+  if (p->force_qr < -1 || p->force_qr > 3) return false;
+  return true;
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace chase
+
+using namespace chase;
+
+struct chase_handle_s {
+  Workspace w;
+  chase_params_t p;
+};
+
+extern "C" {
+
+int chase_default_params(chase_params_t* p) {
+  if (!p) return -1;
+  std::memset(p, 0, sizeof(*p));
+  p->nev = 1;
+  p->nex = 0;
+  p->deg = 20;
+  p->max_deg = 36;
+  p->deg_extra = 2;
+  p->max_iter = 25;
+  p->opt = 1;
+  p->precision = CHASE_FP64;
+  p->lanczos_steps = 25;
+  p->force_qr = CHASE_QR_AUTO;
+  p->bounds_given = 0;
+  p->tol = 1e-10;
+  p->mixed_switch = 1e-6;
+  p->seed = 2309;
+  return 0;
+}
+
+int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h) {
+  if (N < 2) return -1;
+  if (!valid_params(p) || (int64_t)p->nev + p->nex >= N) return -2;
+  if (!h) return -3;
+  auto* hh = new chase_handle_s();
+  hh->p = *p;
+  int st = hh->w.create(N, p->nev + p->nex, p->precision == CHASE_FP32_MIXED, true);
+  if (st) {
+    delete hh;
+    *h = nullptr;
+    return st;
+  }
+  *h = hh;
+  return kOk;
+}
+
+int chase_destroy(chase_handle_t h) {
+  if (!h) return -1;
+  h->w.release();
+  delete h;
+  return kOk;
+}
+
+int chase_solve(chase_handle_t h, const void* A_, int64_t lda, void* V_, int64_t ldv, int32_t use_v0,
+                const void* starts_, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
+                chase_stats_t* stats, chase_stream_t stream_) {
+  if (!h) return -1;
+  Workspace& w = h->w;
+  const chase_params_t P = h->p;
+  const int64_t N = w.N;
+  const int nev = P.nev, ne = P.nev + P.nex;
+  if (!A_ || !aligned16(A_)) return -2;
+  if (lda < N) return -3;
+  if (!V_ || !aligned16(V_)) return -4;
+  if (ldv < N) return -5;
+  if (starts_ && !aligned16(starts_)) return -7;
+  if (starts_ && ld_starts < N) return -8;
+  if (starts_ && (nstarts < 1 || nstarts > 8)) return -9;
+  if (!ritzv) return -10;
+  if (!resid) return -11;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+  const z64* A = reinterpret_cast<const z64*>(A_);
+  z64* V = reinterpret_cast<z64*>(V_);
+  const bool mixed = P.precision == CHASE_FP32_MIXED;
+
+  chase_stats_t S;
+  std::memset(&S, 0, sizeof(S));
+  PhaseTimer t_all, t_lz, t_f, t_qr, t_rr;
+  int st = kOk;
+  for (PhaseTimer* t : {&t_all, &t_lz, &t_f, &t_qr, &t_rr})
+    if ((st = t->init())) return st;
+  auto cleanup = [&]() {
+    for (PhaseTimer* t : {&t_all, &t_lz, &t_f, &t_qr, &t_rr}) t->destroy();
+  };
+  auto fail = [&](int code) {
+    cleanup();
+    return code;
+  };
+
+  t_all.start(s);
+  if (!use_v0) {
+    if ((st = fill_gaussian(V, ldv, N, ne, P.seed, s))) return fail(st);
+  }
+  // ---- Lanczos bounds (Alg. 2, first line)
+  double bnd[4];
+  int64_t total_mv = 0;
+  if (P.bounds_given) {
+    bnd[0] = P.b_sup;
+    bnd[1] = P.mu_1;
+    bnd[2] = P.mu_ne;
+    bnd[3] = P.norm_est;
+  } else {
+    const z64* starts = reinterpret_cast<const z64*>(starts_);
+    int64_t lds = ld_starts;
+    int ns = nstarts;
+    if (!starts) {
+      if ((st = fill_gaussian(w.starts, N, N, 4, P.seed ^ 0x5DEECE66Dull, s))) return fail(st);
+      starts = w.starts;
+      lds = N;
+      ns = 4;
+    }
+    t_lz.start(s);
+    if ((st = lanczos(w, A, lda, starts, lds, ns, P.lanczos_steps, ne, bnd, s))) return fail(st);
+    t_lz.stop(s);
+    total_mv += (int64_t)ns * std::min<int64_t>(P.lanczos_steps, N);
+  }
+  const double b_sup = bnd[0];
+  double mu_1 = bnd[1], mu_ne = bnd[2];
+  const double tol_abs = P.tol * bnd[3];
+
+  // mixed precision: FP32 copy of H
+  if (mixed) {
+    if ((st = convert_z_to_c(A, lda, w.A32, N, N, N, s))) return fail(st);
+  }
+
+  std::vector<int32_t> degs(ne, P.deg);
+  std::vector<double> Lam(ne, 0.0), resd(ne, std::numeric_limits<double>::infinity());
+  std::vector<char> low(ne, mixed ? 1 : 0);  // column still filtered in FP32
+  std::vector<double> prev_resd(ne, std::numeric_limits<double>::infinity());
+  int locked = 0, it = 1;
+  double c = 0.5 * (b_sup + mu_ne), e = 0.5 * (b_sup - mu_ne);
+  double mu1_cur = mu_1;
+  const double sw_abs = P.mixed_switch * bnd[3];
+
+  // C2 <- V (Alg. 2 keeps the saved copy; its active part is rewritten before use)
+  if ((st = copy_columns(V, ldv, w.C2, N, N, ne, s))) return fail(st);
+
+  std::vector<double> th_h(ne), rs_h(ne);
+  bool breakdown = false;
+  while (locked < nev && it <= P.max_iter) {
+    const int na = ne - locked;
+    if (it != 1) {
+      mu1_cur = *std::min_element(Lam.begin(), Lam.end());
+      mu_ne = *std::max_element(Lam.begin(), Lam.end());
+      c = 0.5 * (b_sup + mu_ne);
+      e = 0.5 * (b_sup - mu_ne);
+      if (P.opt)
+        for (int j = locked; j < ne; ++j)
+          degs[j] = degree_opt(resd[j], Lam[j], c, e, tol_abs, P.max_deg, P.deg_extra);
+      // stable sort of the active columns by (precision group, degree)
+      std::vector<int> order(na);
+      std::iota(order.begin(), order.end(), 0);
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (mixed && low[locked + x] != low[locked + y]) return low[locked + x] > low[locked + y];
+        return degs[locked + x] < degs[locked + y];
+      });
+      bool ident = true;
+      for (int j = 0; j < na; ++j) ident = ident && order[j] == j;
+      if (!ident) {
+        if ((st = apply_perm(w, V + (int64_t)locked * ldv, ldv, order, false, 0, s))) return fail(st);
+        auto permute = [&](auto& arr) {
+          auto tmp = arr;
+          for (int j = 0; j < na; ++j) arr[locked + j] = tmp[locked + order[j]];
+        };
+        permute(Lam);
+        permute(resd);
+        permute(degs);
+        permute(low);
+        permute(prev_resd);
+      }
+    }
+
+    // ---- Filter on the active columns
+    t_f.start(s);
+    int64_t mv = 0, nl = 0;
+    if (mixed) {
+      int nlow = 0;
+      while (nlow < na && low[locked + nlow]) ++nlow;
+      int64_t mv32 = 0, nl32 = 0;
+      if (nlow > 0) {
+        if ((st = run_filter_fp32(w.A32, N, V + (int64_t)locked * ldv, ldv, w.X32a, w.X32b, nlow,
+                                  degs.data() + locked, c, e, mu1_cur, &mv32, &nl32, s)))
+          return fail(st);
+      }
+      if (na - nlow > 0) {
+        if ((st = run_filter(A, lda, V + (int64_t)(locked + nlow) * ldv, ldv, w.B + (int64_t)(locked + nlow) * N, N, N,
+                             na - nlow, degs.data() + locked + nlow, c, e, mu1_cur, &mv, &nl, s)))
+          return fail(st);
+      }
+      S.filter_matvecs_fp32 += mv32;
+      mv += mv32;
+      nl += nl32;
+    } else {
+      if ((st = run_filter(A, lda, V + (int64_t)locked * ldv, ldv, w.B + (int64_t)locked * N, N, N, na,
+                           degs.data() + locked, c, e, mu1_cur, &mv, &nl, s)))
+        return fail(st);
+    }
+    t_f.stop(s);
+    S.filter_matvecs += mv;
+    S.filter_launches += nl;
+    total_mv += mv;
+
+    // ---- CondEst and 1D-CAQR on all n_e columns
+    std::vector<double> Lam_est = Lam;
+    if (it == 1) std::fill(Lam_est.begin(), Lam_est.end(), mu1_cur);
+    const double cond = cond_est(Lam_est.data(), c, e, degs.data(), ne, locked);
+    t_qr.start(s);
+    int variant = 0;
+    if ((st = caqr(w, V, ldv, ne, cond, P.force_qr, &variant, s))) return fail(st);
+    t_qr.stop(s);
+    S.qr_count[variant] += 1;
+
+    // ---- restore locked columns, save the new active ones
+    if (locked > 0 && (st = copy_columns(w.C2, N, V, ldv, N, locked, s))) return fail(st);
+    if ((st = copy_columns(V + (int64_t)locked * ldv, ldv, w.C2 + (int64_t)locked * N, N, N, na, s)))
+      return fail(st);
+
+    // ---- Rayleigh-Ritz and residuals
+    t_rr.start(s);
+    if ((st = rayleigh_ritz(w, A, lda, w.C2 + (int64_t)locked * N, N, V + (int64_t)locked * ldv, ldv, na, s)))
+      return fail(st);
+    t_rr.stop(s);
+    total_mv += 2 * (int64_t)na;
+    CHASE_CHK(hipMemcpyAsync(th_h.data(), w.theta, na * sizeof(double), hipMemcpyDeviceToHost, s));
+    CHASE_CHK(hipMemcpyAsync(rs_h.data(), w.resd, na * sizeof(double), hipMemcpyDeviceToHost, s));
+    CHASE_CHK(hipStreamSynchronize(s));
+    for (PhaseTimer* t : {&t_lz, &t_f, &t_qr, &t_rr}) t->collect();
+    for (int j = 0; j < na; ++j) {
+      Lam[locked + j] = th_h[j];
+      prev_resd[locked + j] = resd[locked + j];
+      resd[locked + j] = rs_h[j];
+      if (!std::isfinite(th_h[j]) || !std::isfinite(rs_h[j])) breakdown = true;
+    }
+    if (breakdown) break;
+    if (mixed) {  // switch a column to FP64 once FP32 stops paying
+      for (int j = locked; j < ne; ++j)
+        if (low[j] && (resd[j] <= sw_abs || resd[j] > 0.5 * prev_resd[j])) low[j] = 0;
+    }
+
+    // ---- Deflation and locking
+    std::vector<int> order;
+    std::vector<char> taken(na, 0);
+    int n_new = 0;
+    for (int j = 0; j < std::min(nev - locked, na); ++j)
+      if (resd[locked + j] <= tol_abs) {
+        order.push_back(j);
+        taken[j] = 1;
+        ++n_new;
+      }
+    for (int j = 0; j < na; ++j)
+      if (!taken[j]) order.push_back(j);
+    if (n_new > 0) {
+      bool ident = true;
+      for (int j = 0; j < na; ++j) ident = ident && order[j] == j;
+      if (!ident) {
+        if ((st = apply_perm(w, V + (int64_t)locked * ldv, ldv, order, true, locked, s))) return fail(st);
+        auto permute = [&](auto& arr) {
+          auto tmp = arr;
+          for (int j = 0; j < na; ++j) arr[locked + j] = tmp[locked + order[j]];
+        };
+        permute(Lam);
+        permute(resd);
+        permute(degs);
+        permute(low);
+        permute(prev_resd);
+      }
+    }
+    locked += n_new;
+    ++it;
+  }
+
+  // ---- output: ascending eigenvalues in V[:, 0:nev]
+  const bool converged = locked >= nev;
+  std::vector<int> idx(converged ? locked : ne);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return Lam[x] < Lam[y]; });
+  idx.resize(nev);
+  if ((st = apply_perm(w, V, ldv, std::vector<int>(idx.begin(), idx.end()), false, 0, s))) return fail(st);
+  for (int j = 0; j < nev; ++j) {
+    ritzv[j] = Lam[idx[j]];
+    resid[j] = resd[idx[j]];
+  }
+  t_all.stop(s);
+  CHASE_CHK(hipStreamSynchronize(s));
+  for (PhaseTimer* t : {&t_all, &t_lz, &t_f, &t_qr, &t_rr}) t->collect();
+  S.status = breakdown ? kBreakdown : (converged ? kOk : kNotConverged);
+  S.iterations = it - 1;
+  S.locked = locked;
+  S.total_matvecs = total_mv;
+  S.filter_flops = 8.0 * (double)N * (double)N * (double)S.filter_matvecs;
+  S.t_total = t_all.acc;
+  S.t_lanczos = t_lz.acc;
+  S.t_filter = t_f.acc;
+  S.t_qr = t_qr.acc;
+  S.t_rr = t_rr.acc;
+  S.t_resid = 0.0;  // fused into the Rayleigh-Ritz phase (reassociated H V)
+  for (int i = 0; i < 4; ++i) S.bounds[i] = bnd[i];
+  if (stats) *stats = S;
+  cleanup();
+  return S.status;
+}
+
+int chase_eigval_grad(int64_t N, int32_t nev, const void* X, int64_t ldx, const double* g, void* G, int64_t ldg,
+                      int32_t fill, chase_stream_t stream) {
+  if (N < 1) return -1;
+  if (nev < 1 || nev > N) return -2;
+  if (!X || !aligned16(X)) return -3;
+  if (ldx < N) return -4;
+  if (!g) return -5;
+  if (!G || !aligned16(G)) return -6;
+  if (ldg < N) return -7;
+  if (fill != 0 && fill != 1) return -8;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  GemmArgs a;  // G = X (diag(g) X^H): the scale is applied to the B operand's K index
+  a.M = N; a.N = N; a.K = nev;
+  a.A = reinterpret_cast<const z64*>(X); a.lda = ldx;
+  a.B = reinterpret_cast<const z64*>(X); a.ldb = ldx;
+  a.bscale = g;
+  a.Y = reinterpret_cast<z64*>(G); a.ldy = ldg;
+  a.lower_only = fill == 1 ? 1 : 0;
+  return zgemm_launch(0, 1, a, s);
+}
+
+// ---- step entry points -------------------------------------------------------
+
+int chase_filter(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int64_t ldw, int64_t N, int64_t n,
+                 const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs, chase_stream_t stream) {
+  if (!A || !aligned16(A)) return -1;
+  if (lda < N) return -2;
+  if (!V || !aligned16(V)) return -3;
+  if (ldv < N) return -4;
+  if (!W || !aligned16(W)) return -5;
+  if (ldw < N) return -6;
+  if (N < 1) return -7;
+  if (n < 0) return -8;
+  if (n > 0 && !degs) return -9;
+  // even degrees >= 2, ascending: every column's last iterate lands in V
+  for (int64_t j = 0; j < n; ++j)
+    if (degs[j] < 2 || degs[j] % 2 || (j > 0 && degs[j] < degs[j - 1])) return -9;
+  if (!(e > 0)) return -11;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int64_t mv = 0, nl = 0;
+  int st = run_filter(reinterpret_cast<const z64*>(A), lda, reinterpret_cast<z64*>(V), ldv,
+                      reinterpret_cast<z64*>(W), ldw, N, n, degs, c, e, mu_1, &mv, &nl, s);
+  if (st) return st;
+  CHASE_CHK(hipStreamSynchronize(s));
+  if (matvecs) *matvecs = mv;
+  return kOk;
+}
+
+int chase_caqr(void* V, int64_t ldv, int64_t N, int64_t n, double cond, int32_t force, int32_t* variant,
+               chase_stream_t stream) {
+  if (!V || !aligned16(V)) return -1;
+  if (ldv < N) return -2;
+  if (N < 1) return -3;
+  if (n < 1 || n > N) return -4;
+  if (force < -1 || force > 3) return -6;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Workspace w;
+  int st = w.create(N, (int)n, false, false);
+  if (st) return st;
+  int v = 0;
+  st = caqr(w, reinterpret_cast<z64*>(V), ldv, n, cond, force, &v, s);
+  if (!st) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      set_last_error("chase_caqr", e);
+      st = kHipError;
+    }
+  }
+  w.release();
+  if (!st && variant) *variant = v;
+  return st;
+}
+
+int chase_rayleigh_ritz(const void* A, int64_t lda, void* Q, int64_t ldq, int64_t N, int64_t n, double* theta,
+                        double* resid, chase_stream_t stream) {
+  if (!A || !aligned16(A)) return -1;
+  if (lda < N) return -2;
+  if (!Q || !aligned16(Q)) return -3;
+  if (ldq < N) return -4;
+  if (N < 1) return -5;
+  if (n < 1 || n > N) return -6;
+  if (!theta) return -7;
+  if (!resid) return -8;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Workspace w;
+  int st = w.create(N, (int)n, false, false);
+  if (st) return st;
+  // Q doubles as C2_a: copy it to the workspace's C2 and write Ritz vectors to Q.
+  st = copy_columns(reinterpret_cast<const z64*>(Q), ldq, w.C2, N, N, n, s);
+  if (!st)
+    st = rayleigh_ritz(w, reinterpret_cast<const z64*>(A), lda, w.C2, N, reinterpret_cast<z64*>(Q), ldq, n, s);
+  if (!st) {
+    if (hipMemcpyAsync(theta, w.theta, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(resid, w.resd, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_msg("chase_rayleigh_ritz: copy-out failed");
+      st = kHipError;
+    }
+  }
+  w.release();
+  return st;
+}
+
+int chase_lanczos(const void* A, int64_t lda, int64_t N, const void* starts, int64_t ld_starts, int32_t nstarts,
+                  int32_t ksteps, int32_t ne, double* out, chase_stream_t stream) {
+  if (!A || !aligned16(A)) return -1;
+  if (lda < N) return -2;
+  if (N < 2) return -3;
+  if (!starts || !aligned16(starts)) return -4;
+  if (ld_starts < N) return -5;
+  if (nstarts < 1 || nstarts > 8) return -6;
+  if (ksteps < 1 || ksteps > 256) return -7;
+  if (ne < 1 || ne >= N) return -8;
+  if (!out) return -9;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Workspace w;
+  int st = w.create(N, ne, false, true);
+  if (st) return st;
+  st = lanczos(w, reinterpret_cast<const z64*>(A), lda, reinterpret_cast<const z64*>(starts), ld_starts, nstarts,
+               ksteps, ne, out, s);
+  w.release();
+  return st;
+}
+
+double chase_cond_est(const double* lam, double c, double e, const int32_t* degs, int32_t ne, int32_t locked) {
+  if (!lam || !degs || ne < 1 || locked < 0 || locked >= ne || !(e > 0)) return std::nan("");
+  return cond_est(lam, c, e, degs, ne, locked);
+}
+
+const char* chase_status_string(int status) {
+  switch (status) {
+    case 0: return "ok";
+    case 1: return "not converged within max_iter";
+    case 2: return "device allocation failed";
+    case 3: return "HIP runtime error";
+    case 4: return "numerical breakdown";
+    default: return status < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+const char* chase_last_error(void) { return chase::last_error(); }
+
+}  // extern "C"

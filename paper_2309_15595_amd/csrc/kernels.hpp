@@ -1,0 +1,86 @@
+// Launchers of the hand-written gfx950 kernels used by the ChASE driver.
+#pragma once
+#include "common.hpp"
+
+namespace chase {
+
+// Arguments of the complex FP64 GEMM (see zgemm.hip):
+//   Y = alpha * opA(A) opB(B) + beta * Y + gamma * Z       (M x N, K inner)
+struct GemmArgs {
+  int64_t M = 0, N = 0, K = 0;
+  const z64* A = nullptr; int64_t lda = 0;
+  const z64* B = nullptr; int64_t ldb = 0;
+  z64* Y = nullptr;       int64_t ldy = 0;
+  const z64* Z = nullptr; int64_t ldz = 0;
+  double alpha = 1.0, beta = 0.0, gamma = 0.0;
+  z64* ws = nullptr;      int64_t ws_stride = 0; int64_t k_chunk = 0;
+  const double* bscale = nullptr;  // optional: opB(B)[k][n] *= bscale[k] (diag(g) X^H)
+  int upper_b = 0;     // opB(B) upper triangular: skip its zero K range
+  int lower_only = 0;  // skip tiles strictly above the diagonal (m < n everywhere)
+};
+
+// opa/opb: 0 = as stored, 1 = conjugate transpose.
+int zgemm_launch(int opa, int opb, const GemmArgs& g, hipStream_t s, bool filter_symbol = false);
+// Split over K into `splits` partial products in `ws`, summed in fixed order;
+// hermitise = 1 stores (S + S^H)/2 (M == N).
+int zgemm_splitk(int opa, int opb, const GemmArgs& g, void* ws, int splits, int hermitise,
+                 hipStream_t s);
+int64_t zgemm_splitk_workspace(int64_t M, int64_t N, int splits);
+int choose_splits(int64_t M, int64_t N, int64_t K, int max_splits);
+
+// Complex FP32 GEMM (mixed-precision filter): same contract with complex64 data.
+struct CGemmArgs {
+  int64_t M = 0, N = 0, K = 0;
+  const c32* A = nullptr; int64_t lda = 0;
+  const c32* B = nullptr; int64_t ldb = 0;
+  c32* Y = nullptr;       int64_t ldy = 0;
+  const c32* Z = nullptr; int64_t ldz = 0;
+  float alpha = 1.0f, beta = 0.0f, gamma = 0.0f;
+};
+int cgemm_filter_launch(const CGemmArgs& g, hipStream_t s);
+
+// ---- small dense kernels (small.hip) --------------------------------------
+// Blocked lower Cholesky G = L L^H in place (lower part), n x n, ld.
+// *info (device) receives 0, or j+1 for the first non-positive pivot j.
+int potrf_lower(z64* G, int64_t ld, int64_t n, int* info, z64* ws_gemm, hipStream_t s);
+// Lower-triangular inverse Linv = L^{-1} (n x n); tmp is n x n scratch.
+int trtri_lower(const z64* L, int64_t ldl, z64* Linv, int64_t ldi, int64_t n, z64* tmp,
+                hipStream_t s);
+// G[j][j] += s where s = 11 (m n + n (n+1)) u ||X||_F^2 and ||X||_F^2 = trace(G),
+// computed on the device; shift_out (device, 1 double) keeps s.
+int add_cholqr_shift(z64* G, int64_t ld, int64_t n, int64_t m, double* shift_out, hipStream_t s);
+// Zero the strictly upper part of an n x n matrix.
+int zero_upper(z64* G, int64_t ld, int64_t n, hipStream_t s);
+// out[j] = || Y[:, j] - theta[j] X[:, j] ||_2 for j < n (theta device).
+int residual_norms(const z64* Y, int64_t ldy, const z64* X, int64_t ldx, const double* theta,
+                   int64_t N, int64_t n, double* out, hipStream_t s);
+// dst[:, j] = src[:, perm[j]], j < n (perm device).
+int gather_columns(const z64* src, int64_t lds, z64* dst, int64_t ldd, const int* perm,
+                   int64_t N, int64_t n, hipStream_t s);
+// Column block copy (N x n).
+int copy_columns(const z64* src, int64_t lds, z64* dst, int64_t ldd, int64_t N, int64_t n,
+                 hipStream_t s);
+// W = A V for Hermitian A (reads A's columns), V: N x nv (nv <= 8).
+int hemv_block(const z64* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int64_t ldw,
+               int64_t N, int nv, hipStream_t s);
+// One Lanczos step for nv independent vectors (see small.hip).
+int lanczos_step(z64* V, z64* Vold, z64* W, int64_t N, int nv, int step, int ksteps,
+                 double* alpha, double* beta, hipStream_t s);
+int lanczos_init(const z64* starts, int64_t ld, z64* V, z64* Vold, int64_t N, int nv,
+                 hipStream_t s);
+// Gaussian (re + i im)/sqrt(2) fill from a counter-based generator (splitmix64).
+int fill_gaussian(z64* X, int64_t ld, int64_t N, int64_t n, uint64_t seed, hipStream_t s);
+// X[:, j] *= g[j] (g device, real).
+int scale_columns(const z64* X, int64_t ldx, const double* g, z64* out, int64_t ldo, int64_t N,
+                  int64_t n, hipStream_t s);
+// Non-finite detection over n doubles: *flag (device int) = 1 if any.
+int check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
+// Mirror the lower triangle into the upper one (Hermitian full storage).
+int hermitian_mirror_lower(z64* G, int64_t ld, int64_t n, hipStream_t s);
+// complex128 <-> complex64 conversions (column blocks).
+int convert_z_to_c(const z64* src, int64_t lds, c32* dst, int64_t ldd, int64_t N, int64_t n,
+                   hipStream_t s);
+int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N, int64_t n,
+                   hipStream_t s);
+
+}  // namespace chase

@@ -1,0 +1,91 @@
+"""CPU checks of the C ABI: the built library loads and exports every entry
+point include/chase_hip.h declares; host-only helpers behave."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chase_hip.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return re.findall(r"^\s*(?:int|double|const char\s*\*)\s+(chase_\w+)\s*\(", text, re.M)
+
+
+def _lib():
+    from paper_2309_15595_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libchase_hip.so not built: run python -m paper_2309_15595_amd.build")
+    return L
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("chase_default_params", "chase_create", "chase_solve", "chase_destroy",
+                 "chase_eigval_grad", "chase_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding wraps every one of them
+    assert set(declared_functions()) <= set(L.SIGNATURES)
+
+
+def test_struct_layouts_match_header():
+    L = _lib()
+    # chase_params_t: 12 int32 + 6 double + uint64
+    assert ctypes.sizeof(L.chase_params_t) == 12 * 4 + 6 * 8 + 8
+    # chase_stats_t: 8 int32 + 4 int64 + 7 double + 4 double
+    assert ctypes.sizeof(L.chase_stats_t) == 8 * 4 + 4 * 8 + 7 * 8 + 4 * 8
+
+
+def test_default_params_host_only():
+    L = _lib()
+    p = L.default_params(nev=60, nex=20)
+    assert (p.deg, p.max_deg, p.tol, p.opt, p.max_iter) == (20, 36, 1e-10, 1, 25)
+
+
+def test_status_strings():
+    lib = _lib().load()
+    assert lib.chase_status_string(0) == b"ok"
+    assert lib.chase_status_string(1).startswith(b"not converged")
+    assert lib.chase_status_string(-3) == b"invalid argument"
+
+
+def test_cond_est_matches_oracle_golden():
+    """The library's host CondEst (Alg. 5) on the hand-derived cases."""
+    import json
+    L = _lib()
+    cases = json.load(open(os.path.join(ROOT, "tests", "golden", "condest_cases.json")))["cases"]
+    for case in cases:
+        ne, locked = 5, 2
+        lam = [9.0] * ne
+        lam[0] = case["lam_first"]
+        lam[locked] = case["lam_active"]
+        degs = [case["d"]] * ne
+        degs[-1] = case["d_max"]
+        got = L.chase_cond_est(lam, case["c"], case["e"], degs, locked)
+        assert abs(got - case["expected"]) <= 1e-12 * case["expected"]
+
+
+def test_invalid_arguments_rejected_on_host():
+    """Argument checks run before any device call."""
+    L = _lib()
+    lib = L.load()
+    p = L.default_params(nev=10, nex=5)
+    h = ctypes.c_void_p()
+    assert lib.chase_create(1, ctypes.byref(p), ctypes.byref(h)) == -1
+    assert lib.chase_create(15, ctypes.byref(p), ctypes.byref(h)) == -2   # nev+nex >= N
+    bad = L.default_params(nev=10, nex=5, deg=3)
+    assert lib.chase_create(100, ctypes.byref(bad), ctypes.byref(h)) == -2
+    assert lib.chase_eigval_grad(10, 0, None, 10, None, None, 10, 0, None) == -2
+    assert lib.chase_filter(None, 10, None, 10, None, 10, 10, 1, None, 0.0, 1.0, -1.0, None, None) == -1
+    assert np.isnan(L.chase_cond_est([1.0], 0.0, 0.0, [2], 0))

@@ -1,0 +1,309 @@
+"""GPU parity: each step of the HIP path against the FP64 CPU oracle on the
+same seeded inputs, element by element, through the C ABI.
+
+Tolerances (FP64 everywhere on both sides, different summation orders):
+  * filter: one step is a length-N inner product, error <= ~sqrt(N) u ||A||
+    per entry; over d steps of the bounded scaled recurrence the normwise
+    column error stays below d * N * u ~ 1e-11 for N <= 1000, d <= 36;
+  * CholeskyQR: Q is unique (positive R diagonal), perturbation <= ~kappa u n;
+  * Ritz values: Hermitian perturbation, |d theta| <= ||dG|| ~ N u ||A||;
+  * whole solve: eigenvalues within 1e-10 ||A|| (the paper's tol) of the
+    oracle and of the prescribed spectrum.
+"""
+import numpy as np
+import pytest
+
+import oracle.core as oc
+import synth
+from tests import pins
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_15595_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def cm(x):
+    from paper_2309_15595_amd.api import colmajor
+    return colmajor(np.asarray(x, dtype=np.complex128))
+
+
+def un(t):
+    from paper_2309_15595_amd.api import from_colmajor
+    return from_colmajor(t)
+
+
+def sp():
+    from paper_2309_15595_amd import _lib
+    return _lib.stream_ptr()
+
+
+# ---------------------------------------------------------------- filter
+
+@pytest.mark.parametrize("N,degs", [
+    (517, [2, 2, 4, 6, 6, 10, 20, 20, 36] + [20] * 60 + [36] * 7),   # ragged N, 76 columns
+    (800, [20] * 80),
+    (130, [2, 4]),
+])
+def test_filter_matches_oracle(L, N, degs):
+    rng = np.random.default_rng(N)
+    lam = np.sort(rng.uniform(-1.0, 2.0, N))
+    A = synth.hermitian_from_spectrum(lam, "gaussian", seed=N)
+    degs = np.sort(np.array(degs))
+    n = degs.size
+    V = synth.complex_gaussian(rng, (N, n))
+    c, e, mu1 = 1.1, 0.9, lam[0] + 1e-3
+    ref, mv_ref = oc.chebyshev_filter(A, V, degs, c, e, mu1)
+    Ad, Vd = cm(A), cm(V)
+    Wd = torch.zeros_like(Vd)
+    mv = L.chase_filter(L.dptr(Ad), N, L.dptr(Vd), N, L.dptr(Wd), N, N, n, degs, c, e, mu1, sp())
+    got = un(Vd)
+    assert mv == mv_ref
+    err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= 1e-11, err.max()
+
+
+def test_filter_closed_form_diagonal(L):
+    N = 300
+    lam = np.linspace(-1.2, 3.0, N)
+    A = np.diag(lam).astype(np.complex128)
+    rng = np.random.default_rng(1)
+    degs = np.array([2, 4, 8, 16, 20, 36])
+    V = synth.complex_gaussian(rng, (N, degs.size))
+    c, e, mu1 = 1.0, 2.0, -1.2
+    Ad, Vd = cm(A), cm(V)
+    Wd = torch.zeros_like(Vd)
+    L.chase_filter(L.dptr(Ad), N, L.dptr(Vd), N, L.dptr(Wd), N, N, degs.size, degs, c, e, mu1, sp())
+    got = un(Vd)
+    for j, m in enumerate(degs):
+        p = pins.chebyshev_closed_form((lam - c) / e, m) / pins.chebyshev_closed_form(
+            np.array([(mu1 - c) / e]), m)[0]
+        ref = p * V[:, j]
+        assert np.max(np.abs(got[:, j] - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_filter_leading_dimension(L):
+    """lda, ldv > N: the padding rows are neither read into nor written."""
+    N, n, pad = 200, 9, 13
+    rng = np.random.default_rng(3)
+    A = synth.hermitian_from_spectrum(rng.uniform(-1, 1, N), "gaussian", seed=3)
+    V = synth.complex_gaussian(rng, (N, n))
+    Abig = np.full((N + pad, N), np.nan + 1j * np.nan)
+    Abig[:N] = A
+    Vbig = np.full((N + pad, n), 7.0 + 7.0j)
+    Vbig[:N] = V
+    Ad, Vd = cm(Abig), cm(Vbig)
+    Wd = torch.zeros_like(Vd)
+    degs = [4] * n
+    L.chase_filter(L.dptr(Ad), N + pad, L.dptr(Vd), N + pad, L.dptr(Wd), N + pad, N, n, degs,
+                   0.5, 0.6, -1.0, sp())
+    got = un(Vd)
+    ref, _ = oc.chebyshev_filter(A, V, np.array(degs), 0.5, 0.6, -1.0)
+    assert np.all(got[N:] == 7.0 + 7.0j)
+    assert np.max(np.abs(got[:N] - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------- CAQR
+
+@pytest.mark.parametrize("kappa,force", [(5.0, 0), (1e5, 1), (1e7, 1), (1e12, 2), (1e14, 2),
+                                         (1e3, 3), (1e3, -1)])
+def test_caqr_matches_oracle(L, kappa, force):
+    m, n = 700, 70   # spans several 128/64 tiles plus ragged tails
+    X = pins.matrix_with_cond(m, n, kappa, seed=int(np.log10(kappa) * 10) + 3 + force)
+    Xd = cm(X)
+    v = L.chase_caqr(L.dptr(Xd), m, m, n, kappa, force, sp())
+    Q = un(Xd)
+    orth = np.linalg.norm(Q.conj().T @ Q - np.eye(n), 2)
+    assert orth <= 1e-13, orth
+    R = Q.conj().T @ X
+    assert np.linalg.norm(Q @ R - X) <= 1e-12 * np.linalg.norm(X)
+    ref, vref = oc.caqr(X, kappa, None if force < 0 else force)
+    assert v == vref
+    if v != oc.QR_HOUSEHOLDER:
+        # CholeskyQR's Q is unique: compare element by element
+        assert np.max(np.abs(Q - ref)) <= max(1e-12, 1e-14 * kappa * n) , np.max(np.abs(Q - ref))
+
+
+def test_caqr_fallback_rank_deficient(L):
+    X = pins.matrix_with_cond(300, 20, 10.0, seed=7)
+    X[:, 5] = 0.0
+    Xd = cm(X)
+    v = L.chase_caqr(L.dptr(Xd), 300, 300, 20, 1e3, -1, sp())
+    assert v == oc.QR_HOUSEHOLDER
+    Q = un(Xd)
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(20), 2) <= 1e-13
+
+
+# ---------------------------------------------------------------- Rayleigh-Ritz
+
+@pytest.mark.parametrize("N,n", [(800, 80), (333, 37)])
+def test_rayleigh_ritz_matches_oracle(L, N, n):
+    rng = np.random.default_rng(N + n)
+    lam = np.linspace(-1, 1, N)
+    A = synth.hermitian_from_spectrum(lam, "gaussian", seed=N)
+    Q, _ = np.linalg.qr(synth.complex_gaussian(rng, (N, n)))
+    theta_ref, X_ref = oc.rayleigh_ritz(A, Q)
+    r_ref = oc.residual_norms(A, X_ref, theta_ref)
+    Ad, Qd = cm(A), cm(Q)
+    theta, resid = L.chase_rayleigh_ritz(L.dptr(Ad), N, L.dptr(Qd), N, N, n, sp())
+    X = un(Qd)
+    assert np.max(np.abs(np.array(theta) - theta_ref)) <= 1e-13
+    assert np.max(np.abs(np.array(resid) - r_ref)) <= 1e-12
+    # Ritz vectors agree up to a unit phase per column (distinct Ritz values)
+    overlap = np.abs(np.sum(X.conj() * X_ref, axis=0))
+    assert np.max(np.abs(overlap - 1.0)) <= 1e-10
+    # and the residuals are the true ones for the GPU's vectors
+    r_true = np.linalg.norm(A @ X - X * np.array(theta), axis=0)
+    assert np.max(np.abs(r_true - np.array(resid))) <= 1e-12
+
+
+# ---------------------------------------------------------------- Lanczos
+
+def test_lanczos_matches_oracle(L, parity_problem):
+    p = parity_problem
+    ref = oc.lanczos_bounds(p.A, p.starts, p.ne, 25)
+    Ad, Sd = cm(p.A), cm(p.starts)
+    got = L.chase_lanczos(L.dptr(Ad), p.N, p.N, L.dptr(Sd), p.N, 4, 25, p.ne, sp())
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12), (got, ref)
+    assert got[0] >= p.lam[-1] - 1e-12
+
+
+# ---------------------------------------------------------------- whole solve
+
+def solve_gpu(p, **kw):
+    from paper_2309_15595_amd.api import Solver
+    with Solver(p.N, p.nev, p.nex, **kw) as s:
+        Ad, Vd, Sd = cm(p.A), cm(p.V0), cm(p.starts)
+        ritz, resid, info = s.solve_colmajor(Ad, Vd, True, Sd)
+        X = un(Vd)[:, : p.nev]
+    return ritz, resid, X, info
+
+
+def check_solution(p, ritz, resid, X, tol=1e-10):
+    normA = p.norm2
+    assert np.all(np.diff(ritz) >= 0)
+    assert np.max(np.abs(ritz - p.lam[: p.nev])) <= tol * normA
+    r_true = np.linalg.norm(p.A @ X - X * ritz, axis=0)
+    assert np.max(r_true) <= tol * normA * (1 + 1e-6)
+    assert np.max(np.abs(r_true - resid)) <= 1e-12 * normA
+    assert np.linalg.norm(X.conj().T @ X - np.eye(p.nev), 2) <= 1e-12
+
+
+def test_solve_parity_problem(L, parity_problem, parity_oracle):
+    p, r = parity_problem, parity_oracle
+    ritz, resid, X, info = solve_gpu(p)
+    assert info.converged, info.stats
+    check_solution(p, ritz, resid, X)
+    assert np.max(np.abs(ritz - r.evals)) <= 1e-10 * p.norm2
+    st = info.stats
+    print(f"\nGPU: iters {st['iterations']} matvecs {st['filter_matvecs']} qr {st['qr_count']}; "
+          f"oracle: iters {r.iterations} matvecs {r.filter_matvecs}")
+    # same path up to rounding at the degree ceilings
+    assert abs(st["iterations"] - r.iterations) <= 1
+    assert abs(st["filter_matvecs"] - r.filter_matvecs) <= 0.05 * r.filter_matvecs
+
+
+@pytest.mark.parametrize("N,nev,nex,spectrum", [(333, 13, 7, "dft"), (1000, 90, 26, "uniform"),
+                                                (200, 8, 4, "dft")])
+def test_solve_ragged_sizes(L, N, nev, nex, spectrum):
+    p = synth.make_problem(N, nev, nex, spectrum=spectrum, basis="gaussian", seed=N)
+    ritz, resid, X, info = solve_gpu(p)
+    assert info.converged
+    check_solution(p, ritz, resid, X)
+    r = oc.chase(p.A, oc.Params(nev=nev, nex=nex), V0=p.V0, starts=p.starts)
+    assert np.max(np.abs(ritz - r.evals)) <= 1e-10 * p.norm2
+
+
+@pytest.mark.parametrize("force", [0, 1, 2, 3])
+def test_solve_forced_qr_variants(L, force):
+    p = synth.make_problem(400, 20, 10, spectrum="uniform", seed=11)
+    ritz, resid, X, info = solve_gpu(p, force_qr=force)
+    assert info.converged
+    check_solution(p, ritz, resid, X)
+    assert info.stats["qr_count"][force] == info.stats["iterations"]
+
+
+def test_solve_not_converged_status(L, parity_problem):
+    ritz, resid, X, info = solve_gpu(parity_problem, max_iter=1)
+    assert info.status == 1 and not info.converged
+    assert np.all(np.diff(ritz) >= 0)
+
+
+def test_solve_nan_is_breakdown(L):
+    p = synth.make_problem(150, 6, 4, seed=5)
+    p.A[3, 7] = np.nan
+    from paper_2309_15595_amd import _lib
+    with pytest.raises(_lib.ChaseError):
+        solve_gpu(p)
+
+
+def test_solve_random_start_from_seed(L):
+    """use_v0 = 0: the library draws the block and the Lanczos starts itself."""
+    from paper_2309_15595_amd.api import Solver
+    p = synth.make_problem(300, 12, 6, seed=9)
+    with Solver(p.N, p.nev, p.nex) as s:
+        Ad = cm(p.A)
+        Vd = torch.empty((p.ne, p.N), dtype=torch.complex128, device="cuda")
+        ritz, resid, info = s.solve_colmajor(Ad, Vd, use_v0=False)
+    assert info.converged
+    assert np.max(np.abs(ritz - p.lam[: p.nev])) <= 1e-10 * p.norm2
+
+
+def test_eigsh_torch_layout(L):
+    """eigsh on a row-major torch tensor returns A's (not conj(A)'s) vectors."""
+    from paper_2309_15595_amd.api import eigsh
+    p = synth.make_problem(256, 10, 6, seed=4)
+    A = torch.from_numpy(p.A).cuda()
+    evals, evecs, info = eigsh(A, 10, 6, V0=torch.from_numpy(p.V0).cuda(),
+                               starts=torch.from_numpy(p.starts).cuda())
+    X = evecs.cpu().numpy()
+    ev = evals.cpu().numpy()
+    assert np.max(np.abs(ev - p.lam[:10])) <= 1e-10 * p.norm2
+    assert np.max(np.linalg.norm(p.A @ X - X * ev, axis=0)) <= 1e-10 * p.norm2
+
+
+# ---------------------------------------------------------------- gradient
+
+@pytest.mark.parametrize("fill", [0, 1])
+def test_eigval_grad_matches_oracle(L, fill):
+    rng = np.random.default_rng(21)
+    N, nev = 300, 40
+    X = synth.complex_gaussian(rng, (N, nev))
+    g = rng.uniform(0, 1, nev)
+    ref = oc.eigval_grad(X, g)
+    Xd = cm(X)
+    gd = torch.from_numpy(g).cuda()
+    Gd = torch.zeros((N, N), dtype=torch.complex128, device="cuda")
+    L.chase_eigval_grad(N, nev, L.dptr(Xd), N, L.dptr(gd), L.dptr(Gd), N, fill, sp())
+    torch.cuda.synchronize()
+    G = un(Gd)
+    if fill == 1:
+        mask = np.tril(np.ones((N, N), dtype=bool))
+        assert np.max(np.abs(G[mask] - ref[mask])) <= 1e-13 * np.max(np.abs(ref))
+    else:
+        assert np.max(np.abs(G - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_autograd_matches_dense_eigh(L):
+    from paper_2309_15595_amd.api import eigvalsh_lowest
+    p = synth.make_problem(200, 8, 4, spectrum="dft", seed=2312)
+    w = synth.problems.loss_weights(8)
+    A = torch.from_numpy(p.A).cuda().requires_grad_(True)
+    lam = eigvalsh_lowest(A, 8, 4, V0=torch.from_numpy(p.V0).cuda(),
+                          starts=torch.from_numpy(p.starts).cuda())
+    loss = (lam * torch.from_numpy(w).cuda()).sum()
+    loss.backward()
+    Acpu = torch.from_numpy(p.A).requires_grad_(True)
+    ref = torch.linalg.eigvalsh(Acpu)[:8]
+    (ref * torch.from_numpy(w)).sum().backward()
+    assert abs(loss.item() - float((ref * torch.from_numpy(w)).sum())) <= 1e-10 * p.norm2
+    assert torch.max(torch.abs(A.grad.cpu() - Acpu.grad)).item() <= 1e-8
