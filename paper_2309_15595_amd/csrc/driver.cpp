@@ -508,7 +508,7 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   g.A = A; g.lda = lda;
   g.B = Q; g.ldb = ldq;
   g.Y = w.B; g.ldy = N;
-  int st = zgemm_launch(0, 0, g, s);
+  int st = zgemm_nn_big_launch(g, s, false);
   if (st) return st;
   GemmArgs q;  // G = Q^H B, Hermitised
   q.M = n; q.N = n; q.K = N;

@@ -21,6 +21,9 @@ struct GemmArgs {
 
 // opa/opb: 0 = as stored, 1 = conjugate transpose.
 int zgemm_launch(int opa, int opb, const GemmArgs& g, hipStream_t s, bool filter_symbol = false);
+// Large NN products (filter step, H C): 128 x 128 tiles, double-buffered LDS
+// (zfilter.hip).  filter_symbol selects the kernel name reported by profilers.
+int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol);
 // Split over K into `splits` partial products in `ws`, summed in fixed order;
 // hermitise = 1 stores (S + S^H)/2 (M == N).
 int zgemm_splitk(int opa, int opb, const GemmArgs& g, void* ws, int splits, int hermitise,

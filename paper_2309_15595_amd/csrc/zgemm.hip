@@ -231,8 +231,6 @@ __device__ __forceinline__ void zgemm_body(const GemmArgs& g) {
 __global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_nn(GemmArgs g) { zgemm_body<0, 0>(g); }
 __global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_cn(GemmArgs g) { zgemm_body<1, 0>(g); }
 __global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_nc(GemmArgs g) { zgemm_body<0, 1>(g); }
-// The Chebyshev filter step gets its own symbol so profiles separate it.
-__global__ __launch_bounds__(NT, ZGEMM_WAVES) void zfilter_step(GemmArgs g) { zgemm_body<0, 0>(g); }
 
 // Sum of split-K partials (fixed order), optionally Hermitised, written to Y
 // with the epilogue alpha * S + beta * Y.
@@ -279,7 +277,7 @@ int zgemm_launch(int opa, int opb, const GemmArgs& g_in, hipStream_t stream, boo
   }
   g.ws = nullptr;
   if (filter_symbol) {
-    hipLaunchKernelGGL(zfilter_step, blocks, dim3(NT), 0, stream, g);
+    return zgemm_nn_big_launch(g, stream, true);
   } else if (opa == 0 && opb == 0) {
     hipLaunchKernelGGL(zgemm_nn, blocks, dim3(NT), 0, stream, g);
   } else if (opa == 1 && opb == 0) {
