@@ -119,11 +119,27 @@ int chase_solve(chase_handle_t h, const void* A, int64_t lda, void* V, int64_t l
 
 int chase_destroy(chase_handle_t h);
 
+/* Many independent problems of uneven N, each with its own params (FP64),
+ * solved together.  Every degree step of all problems' Chebyshev filters runs
+ * as one persistent grouped launch over a device descriptor table (one GEMM
+ * per problem per step); the launches of all steps are captured once in a HIP
+ * graph and replayed each outer iteration after the table is refreshed.  QR,
+ * Rayleigh-Ritz, residuals and locking run per problem (Alg. 2).  Arrays have
+ * length `count`; pointers as in chase_solve.  starts / ld_starts / nstarts /
+ * use_v0 may be NULL (then: library-drawn starts, use_v0 = 1).  stats[i]
+ * (nullable array) reports the shared filter and total times.  Returns the
+ * worst status over the problems. */
+int chase_solve_batched(int32_t count, const int64_t* N, const void* const* A, const int64_t* lda,
+                        void* const* V, const int64_t* ldv, const int32_t* use_v0,
+                        const void* const* starts, const int64_t* ld_starts, const int32_t* nstarts,
+                        const chase_params_t* params, double* const* ritzv, double* const* resid,
+                        chase_stats_t* stats, chase_stream_t stream);
+
 /* Gradient of L = sum_i g_i lambda_i with respect to H (Hellmann-Feynman:
  * d lambda_i = x_i^H dH x_i):  G = X diag(g) X^H.
  *   X (device) N x nev eigenvectors, g (device) nev doubles, G (device) N x N.
  *   fill = 0 writes the full Hermitian G, 1 only its lower triangle.
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream` (allocates nothing). */
 int chase_eigval_grad(int64_t N, int32_t nev, const void* X, int64_t ldx, const double* g, void* G,
                       int64_t ldg, int32_t fill, chase_stream_t stream);
 

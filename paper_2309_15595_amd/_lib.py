@@ -60,6 +60,10 @@ SIGNATURES = {
     "chase_solve": (C.c_int, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _I32, _DP, _DP,
                               C.POINTER(chase_stats_t), _P]),
     "chase_destroy": (C.c_int, [_P]),
+    "chase_solve_batched": (C.c_int, [_I32, _I64P, C.POINTER(_P), _I64P, C.POINTER(_P), _I64P,
+                                      _I32P, C.POINTER(_P), _I64P, _I32P,
+                                      C.POINTER(chase_params_t), C.POINTER(_DP), C.POINTER(_DP),
+                                      C.POINTER(chase_stats_t), _P]),
     "chase_eigval_grad": (C.c_int, [_I64, _I32, _P, _I64, _P, _P, _I64, _I32, _P]),
     "chase_filter": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D,
                                _I64P, _P]),
@@ -151,6 +155,24 @@ def chase_solve(h, A_ptr, lda, V_ptr, ldv, use_v0, starts_ptr, ld_starts, nstart
                             nstarts, ritz, resid, C.byref(stats), stream)
     check(st, "chase_solve", allow_not_converged=True)
     return list(ritz), list(resid), stats
+
+
+def chase_solve_batched(Ns, A_ptrs, ldas, V_ptrs, ldvs, use_v0, start_ptrs, ld_starts, nstarts,
+                        params, stream):
+    """Arrays over problems; returns (ritz lists, resid lists, stats list, status)."""
+    cnt = len(Ns)
+    arr = lambda T, xs: (T * cnt)(*xs)
+    ritz = [f64_array(p.nev) for p in params]
+    resid = [f64_array(p.nev) for p in params]
+    stats = (chase_stats_t * cnt)()
+    st = load().chase_solve_batched(
+        cnt, arr(C.c_int64, Ns), arr(_P, A_ptrs), arr(C.c_int64, ldas), arr(_P, V_ptrs),
+        arr(C.c_int64, ldvs), arr(C.c_int32, use_v0), arr(_P, [p or None for p in start_ptrs]),
+        arr(C.c_int64, ld_starts), arr(C.c_int32, nstarts), arr(chase_params_t, params),
+        arr(_DP, [C.cast(r, _DP) for r in ritz]), arr(_DP, [C.cast(r, _DP) for r in resid]),
+        stats, stream)
+    check(st, "chase_solve_batched", allow_not_converged=True)
+    return [list(r) for r in ritz], [list(r) for r in resid], list(stats), st
 
 
 def chase_eigval_grad(N, nev, X_ptr, ldx, g_ptr, G_ptr, ldg, fill, stream) -> None:

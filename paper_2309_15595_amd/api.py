@@ -83,6 +83,28 @@ class Solver:
                                                           stats.as_dict())
 
 
+def solve_batched(A_cms, V_cms, nevs, nexs, starts_cms=None, stream=None, **params):
+    """Solve many Hermitian problems of uneven N together (grouped filter).
+
+    A_cms[i]: (N_i, N_i) column-major H_i; V_cms[i]: (n_e_i, N_i) initial
+    blocks (in/out); starts_cms[i]: optional (r_i, N_i).  Returns lists of
+    (ritz values, residuals) and per-problem stats dicts, and the status.
+    """
+    n = len(A_cms)
+    Ns = [int(a.shape[0]) for a in A_cms]
+    for i in range(n):
+        _check_dev(A_cms[i], (Ns[i], Ns[i]))
+        _check_dev(V_cms[i], (nevs[i] + nexs[i], Ns[i]))
+    starts_cms = starts_cms or [None] * n
+    plist = [_lib.default_params(nev=nevs[i], nex=nexs[i], **params) for i in range(n)]
+    ritz, resid, stats, st = _lib.chase_solve_batched(
+        Ns, [_lib.dptr(a) for a in A_cms], Ns, [_lib.dptr(v) for v in V_cms], Ns, [1] * n,
+        [_lib.dptr(s) for s in starts_cms], Ns,
+        [0 if s is None else int(s.shape[0]) for s in starts_cms], plist, _lib.stream_ptr(stream))
+    return ([np.array(r) for r in ritz], [np.array(r) for r in resid],
+            [s.as_dict() for s in stats], st)
+
+
 def _check_dev(t: torch.Tensor, shape):
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError("expected a CUDA (HIP) tensor")

@@ -212,6 +212,8 @@ struct Workspace {
   c32* A32 = nullptr;
   c32* X32a = nullptr;
   c32* X32b = nullptr;
+  void* tail_ws = nullptr;     // split-K tail of the big GEMMs
+  int* tail_counters = nullptr;
   rocblas_handle rb = nullptr;
   std::vector<void*> owned;
 
@@ -248,6 +250,10 @@ struct Workspace {
     st = st ? st : alloc(&info, 1);
     st = st ? st : alloc(&flag, 1);
     st = st ? st : alloc(&perm, (size_t)ne);
+    st = st ? st : alloc(reinterpret_cast<char**>(&tail_ws), (size_t)tail_workspace_bytes());
+    st = st ? st : alloc(&tail_counters, (size_t)kTailMaxSegments);
+    if (!st) st = tail_counters_init(tail_counters, nullptr);
+    if (!st && hipDeviceSynchronize() != hipSuccess) st = kHipError;
     st = st ? st : alloc(&lz_alpha, 8 * 256);
     st = st ? st : alloc(&lz_beta, 8 * 256);
     if (lanczos) {
@@ -281,19 +287,20 @@ struct Workspace {
 // Steps
 // ---------------------------------------------------------------------------
 
-// Filter (Eq. 1 with the scaled Chebyshev coefficients).  V: N x n in place
-// (the final iterate of an even degree lands back in V), W: ping-pong.
-// degs ascending.  Returns the number of GEMM launches in *launches.
-static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N,
-                      int64_t n, const int32_t* degs, double c, double e, double mu1, int64_t* matvecs,
-                      int64_t* launches, hipStream_t s) {
-  if (n <= 0) return kOk;
+// Filter (Eq. 1 with the scaled Chebyshev coefficients): the GEMM of every
+// degree step.  V: N x n (the final iterate of an even degree lands back in
+// V), W: its ping-pong partner; degs ascending.  Step k computes X_{k+1} for
+// the columns whose degree exceeds k, a suffix of the block.
+static std::vector<GemmArgs> plan_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, int64_t ldw,
+                                         int64_t N, int64_t n, const int32_t* degs, double c, double e,
+                                         double mu1) {
+  std::vector<GemmArgs> steps;
+  if (n <= 0) return steps;
   const int dmax = degs[n - 1];
-  int64_t mv = 0, nl = 0;
   const double sigma1 = e / (mu1 - c);
   double sigma = sigma1;
-  for (int k = 0; k < dmax; ++k) {  // computes X_{k+1}
-    int64_t s0 = 0;
+  int64_t s0 = 0;
+  for (int k = 0; k < dmax; ++k) {
     while (s0 < n && degs[s0] < k + 1) ++s0;
     const int64_t cols = n - s0;
     if (cols <= 0) break;
@@ -320,13 +327,23 @@ static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, in
     g.Y = out + s0 * ldo; g.ldy = ldo;
     g.Z = cur + s0 * ldc; g.ldz = ldc;
     g.alpha = alpha; g.beta = beta; g.gamma = -alpha * c;
-    int st = zgemm_launch(0, 0, g, s, true);
+    steps.push_back(g);
+  }
+  return steps;
+}
+
+static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N,
+                      int64_t n, const int32_t* degs, double c, double e, double mu1, int64_t* matvecs,
+                      int64_t* launches, hipStream_t s, void* tail_ws, int* tail_counters) {
+  const std::vector<GemmArgs> steps = plan_filter(A, lda, V, ldv, W, ldw, N, n, degs, c, e, mu1);
+  int64_t mv = 0;
+  for (const GemmArgs& g : steps) {
+    int st = zgemm_nn_big_launch(g, s, true, tail_ws, tail_counters);
     if (st) return st;
-    mv += cols;
-    ++nl;
+    mv += g.N;
   }
   if (matvecs) *matvecs = mv;
-  if (launches) *launches = nl;
+  if (launches) *launches = (int64_t)steps.size();
   return kOk;
 }
 
@@ -508,7 +525,7 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   g.A = A; g.lda = lda;
   g.B = Q; g.ldb = ldq;
   g.Y = w.B; g.ldy = N;
-  int st = zgemm_nn_big_launch(g, s, false);
+  int st = zgemm_nn_big_launch(g, s, false, w.tail_ws, w.tail_counters);
   if (st) return st;
   GemmArgs q;  // G = Q^H B, Hermitised
   q.M = n; q.N = n; q.K = N;
@@ -622,6 +639,273 @@ static bool valid_params(const chase_params_t* p) {
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// State of one problem's ChASE loop (Alg. 2).  The single solve and the
+// batched solve drive the same steps; only the filter launch differs.
+struct ProblemState {
+  Workspace* w = nullptr;
+  chase_params_t P{};
+  const z64* A = nullptr;
+  int64_t lda = 0;
+  z64* V = nullptr;
+  int64_t ldv = 0;
+  int64_t N = 0;
+  int nev = 0, ne = 0;
+  bool mixed = false;
+  std::vector<int32_t> degs;
+  std::vector<double> Lam, resd, prev_resd, th_h, rs_h;
+  std::vector<char> low;  // column still filtered in FP32 (mixed precision)
+  int locked = 0, it = 1;
+  double bnd[4] = {0, 0, 0, 0};
+  double b_sup = 0, mu_ne = 0, c = 0, e = 1, mu1_cur = 0, tol_abs = 0, sw_abs = 0;
+  bool breakdown = false;
+  chase_stats_t S{};
+  int64_t total_mv = 0;
+  PhaseTimer t_lz, t_f, t_qr, t_rr;
+
+  int init_timers() {
+    int st;
+    for (PhaseTimer* t : {&t_lz, &t_f, &t_qr, &t_rr})
+      if ((st = t->init())) return st;
+    return kOk;
+  }
+  void destroy_timers() {
+    for (PhaseTimer* t : {&t_lz, &t_f, &t_qr, &t_rr}) t->destroy();
+  }
+  void collect_timers() {
+    for (PhaseTimer* t : {&t_lz, &t_f, &t_qr, &t_rr}) t->collect();
+  }
+  bool active() const { return !breakdown && locked < nev && it <= P.max_iter; }
+  int na() const { return ne - locked; }
+
+  template <class T>
+  void permute_active(std::vector<T>& arr, const std::vector<int>& order) {
+    std::vector<T> tmp(arr.begin() + locked, arr.end());
+    for (int j = 0; j < na(); ++j) arr[locked + j] = tmp[order[j]];
+  }
+  void permute_state(const std::vector<int>& order) {
+    permute_active(Lam, order);
+    permute_active(resd, order);
+    permute_active(degs, order);
+    permute_active(low, order);
+    permute_active(prev_resd, order);
+  }
+
+  // Initial block, Lanczos bounds (Alg. 2 first line), FP32 copy of H.
+  int setup(int use_v0, const z64* starts, int64_t lds, int nstarts, hipStream_t s) {
+    int st = kOk;
+    N = w->N;
+    nev = P.nev;
+    ne = P.nev + P.nex;
+    mixed = P.precision == CHASE_FP32_MIXED;
+    std::memset(&S, 0, sizeof(S));
+    if (!use_v0 && (st = fill_gaussian(V, ldv, N, ne, P.seed, s))) return st;
+    if (P.bounds_given) {
+      bnd[0] = P.b_sup;
+      bnd[1] = P.mu_1;
+      bnd[2] = P.mu_ne;
+      bnd[3] = P.norm_est;
+    } else {
+      int64_t ld = lds;
+      int ns = nstarts;
+      if (!starts) {
+        if ((st = fill_gaussian(w->starts, N, N, 4, P.seed ^ 0x5DEECE66Dull, s))) return st;
+        starts = w->starts;
+        ld = N;
+        ns = 4;
+      }
+      t_lz.start(s);
+      if ((st = lanczos(*w, A, lda, starts, ld, ns, P.lanczos_steps, ne, bnd, s))) return st;
+      t_lz.stop(s);
+      total_mv += (int64_t)ns * std::min<int64_t>(P.lanczos_steps, N);
+    }
+    b_sup = bnd[0];
+    mu1_cur = bnd[1];
+    mu_ne = bnd[2];
+    tol_abs = P.tol * bnd[3];
+    sw_abs = P.mixed_switch * bnd[3];
+    c = 0.5 * (b_sup + mu_ne);
+    e = 0.5 * (b_sup - mu_ne);
+    if (mixed && (st = convert_z_to_c(A, lda, w->A32, N, N, N, s))) return st;
+    degs.assign(ne, P.deg);
+    Lam.assign(ne, 0.0);
+    resd.assign(ne, std::numeric_limits<double>::infinity());
+    prev_resd = resd;
+    low.assign(ne, mixed ? 1 : 0);
+    th_h.assign(ne, 0.0);
+    rs_h.assign(ne, 0.0);
+    return copy_columns(V, ldv, w->C2, N, N, ne, s);
+  }
+
+  // Iteration prologue (iterations after the first): new bounds, degree
+  // optimisation and the stable sort of the active columns by degree.
+  int prepare(hipStream_t s) {
+    if (it == 1) return kOk;
+    mu1_cur = *std::min_element(Lam.begin(), Lam.end());
+    mu_ne = *std::max_element(Lam.begin(), Lam.end());
+    c = 0.5 * (b_sup + mu_ne);
+    e = 0.5 * (b_sup - mu_ne);
+    if (P.opt)
+      for (int j = locked; j < ne; ++j) degs[j] = degree_opt(resd[j], Lam[j], c, e, tol_abs, P.max_deg, P.deg_extra);
+    std::vector<int> order(na());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      if (mixed && low[locked + x] != low[locked + y]) return low[locked + x] > low[locked + y];
+      return degs[locked + x] < degs[locked + y];
+    });
+    bool ident = true;
+    for (int j = 0; j < na(); ++j) ident = ident && order[j] == j;
+    if (ident) return kOk;
+    int st = apply_perm(*w, V + (int64_t)locked * ldv, ldv, order, false, 0, s);
+    if (st) return st;
+    permute_state(order);
+    return kOk;
+  }
+
+  int n_low() const {
+    int k = 0;
+    while (k < na() && low[locked + k]) ++k;
+    return k;
+  }
+
+  // FP64 filter GEMMs of this iteration (the columns not in FP32).
+  std::vector<GemmArgs> plan() {
+    const int nl = mixed ? n_low() : 0;
+    return plan_filter(A, lda, V + (int64_t)(locked + nl) * ldv, ldv, w->B + (int64_t)(locked + nl) * N, N, N,
+                       na() - nl, degs.data() + locked + nl, c, e, mu1_cur);
+  }
+
+  // Filter launched eagerly on `s` (single-problem solve).
+  int filter_eager(hipStream_t s) {
+    t_f.start(s);
+    int st = kOk;
+    int64_t mv = 0, nl = 0;
+    const int nlow = mixed ? n_low() : 0;
+    if (nlow > 0) {
+      int64_t mv32 = 0, nl32 = 0;
+      if ((st = run_filter_fp32(w->A32, N, V + (int64_t)locked * ldv, ldv, w->X32a, w->X32b, nlow,
+                                degs.data() + locked, c, e, mu1_cur, &mv32, &nl32, s)))
+        return st;
+      S.filter_matvecs_fp32 += mv32;
+      mv += mv32;
+      nl += nl32;
+    }
+    for (const GemmArgs& g : plan()) {
+      if ((st = zgemm_nn_big_launch(g, s, true, w->tail_ws, w->tail_counters))) return st;
+      mv += g.N;
+      ++nl;
+    }
+    t_f.stop(s);
+    S.filter_matvecs += mv;
+    S.filter_launches += nl;
+    total_mv += mv;
+    return kOk;
+  }
+
+  // CondEst, 1D-CAQR, restore/save, Rayleigh-Ritz, residuals, locking.
+  int post_filter(hipStream_t s) {
+    int st = kOk;
+    std::vector<double> Lam_est = Lam;
+    if (it == 1) std::fill(Lam_est.begin(), Lam_est.end(), mu1_cur);
+    const double cond = cond_est(Lam_est.data(), c, e, degs.data(), ne, locked);
+    t_qr.start(s);
+    int variant = 0;
+    if ((st = caqr(*w, V, ldv, ne, cond, P.force_qr, &variant, s))) return st;
+    t_qr.stop(s);
+    S.qr_count[variant] += 1;
+
+    // restore the locked columns, save the new active ones
+    if (locked > 0 && (st = copy_columns(w->C2, N, V, ldv, N, locked, s))) return st;
+    if ((st = copy_columns(V + (int64_t)locked * ldv, ldv, w->C2 + (int64_t)locked * N, N, N, na(), s))) return st;
+
+    t_rr.start(s);
+    if ((st = rayleigh_ritz(*w, A, lda, w->C2 + (int64_t)locked * N, N, V + (int64_t)locked * ldv, ldv, na(), s)))
+      return st;
+    t_rr.stop(s);
+    total_mv += 2 * (int64_t)na();
+    CHASE_CHK(hipMemcpyAsync(th_h.data(), w->theta, na() * sizeof(double), hipMemcpyDeviceToHost, s));
+    CHASE_CHK(hipMemcpyAsync(rs_h.data(), w->resd, na() * sizeof(double), hipMemcpyDeviceToHost, s));
+    CHASE_CHK(hipStreamSynchronize(s));
+    collect_timers();
+    for (int j = 0; j < na(); ++j) {
+      Lam[locked + j] = th_h[j];
+      prev_resd[locked + j] = resd[locked + j];
+      resd[locked + j] = rs_h[j];
+      if (!std::isfinite(th_h[j]) || !std::isfinite(rs_h[j])) breakdown = true;
+    }
+    if (breakdown) return kOk;
+    if (mixed)  // a column leaves FP32 once at the FP32 floor or no longer improving
+      for (int j = locked; j < ne; ++j)
+        if (low[j] && (resd[j] <= sw_abs || resd[j] > 0.5 * prev_resd[j])) low[j] = 0;
+
+    // Deflation and locking
+    std::vector<int> order;
+    std::vector<char> taken(na(), 0);
+    int n_new = 0;
+    for (int j = 0; j < std::min(nev - locked, na()); ++j)
+      if (resd[locked + j] <= tol_abs) {
+        order.push_back(j);
+        taken[j] = 1;
+        ++n_new;
+      }
+    for (int j = 0; j < na(); ++j)
+      if (!taken[j]) order.push_back(j);
+    if (n_new > 0) {
+      bool ident = true;
+      for (int j = 0; j < na(); ++j) ident = ident && order[j] == j;
+      if (!ident) {
+        if ((st = apply_perm(*w, V + (int64_t)locked * ldv, ldv, order, true, locked, s))) return st;
+        permute_state(order);
+      }
+    }
+    locked += n_new;
+    ++it;
+    return kOk;
+  }
+
+  // Output: the nev lowest pairs, ascending, in V[:, 0:nev].
+  int finish(double* ritzv, double* resid, hipStream_t s) {
+    const bool converged = locked >= nev;
+    std::vector<int> idx(converged ? locked : ne);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return Lam[x] < Lam[y]; });
+    idx.resize(nev);
+    int st = apply_perm(*w, V, ldv, idx, false, 0, s);
+    if (st) return st;
+    for (int j = 0; j < nev; ++j) {
+      ritzv[j] = Lam[idx[j]];
+      resid[j] = resd[idx[j]];
+    }
+    collect_timers();
+    S.status = breakdown ? kBreakdown : (converged ? kOk : kNotConverged);
+    S.iterations = it - 1;
+    S.locked = locked;
+    S.total_matvecs = total_mv;
+    S.filter_flops = 8.0 * (double)N * (double)N * (double)S.filter_matvecs;
+    S.t_lanczos = t_lz.acc;
+    S.t_filter += t_f.acc;
+    S.t_qr = t_qr.acc;
+    S.t_rr = t_rr.acc;
+    S.t_resid = 0.0;  // inside the Rayleigh-Ritz phase: the residual reuses H C2
+    for (int i = 0; i < 4; ++i) S.bounds[i] = bnd[i];
+    return kOk;
+  }
+};
+
+static int check_solve_args(int64_t N, const void* A, int64_t lda, const void* V, int64_t ldv, const void* starts,
+                            int64_t ld_starts, int32_t nstarts, const double* ritzv, const double* resid) {
+  if (!A || !aligned16(A)) return -2;
+  if (lda < N) return -3;
+  if (!V || !aligned16(V)) return -4;
+  if (ldv < N) return -5;
+  if (starts && !aligned16(starts)) return -7;
+  if (starts && ld_starts < N) return -8;
+  if (starts && (nstarts < 1 || nstarts > 8)) return -9;
+  if (!ritzv) return -10;
+  if (!resid) return -11;
+  return kOk;
+}
+
+
 }  // namespace chase
 
 using namespace chase;
@@ -680,249 +964,194 @@ int chase_solve(chase_handle_t h, const void* A_, int64_t lda, void* V_, int64_t
                 const void* starts_, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
                 chase_stats_t* stats, chase_stream_t stream_) {
   if (!h) return -1;
-  Workspace& w = h->w;
-  const chase_params_t P = h->p;
-  const int64_t N = w.N;
-  const int nev = P.nev, ne = P.nev + P.nex;
-  if (!A_ || !aligned16(A_)) return -2;
-  if (lda < N) return -3;
-  if (!V_ || !aligned16(V_)) return -4;
-  if (ldv < N) return -5;
-  if (starts_ && !aligned16(starts_)) return -7;
-  if (starts_ && ld_starts < N) return -8;
-  if (starts_ && (nstarts < 1 || nstarts > 8)) return -9;
-  if (!ritzv) return -10;
-  if (!resid) return -11;
+  int st = check_solve_args(h->w.N, A_, lda, V_, ldv, starts_, ld_starts, nstarts, ritzv, resid);
+  if (st) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
-  const z64* A = reinterpret_cast<const z64*>(A_);
-  z64* V = reinterpret_cast<z64*>(V_);
-  const bool mixed = P.precision == CHASE_FP32_MIXED;
-
-  chase_stats_t S;
-  std::memset(&S, 0, sizeof(S));
-  PhaseTimer t_all, t_lz, t_f, t_qr, t_rr;
-  int st = kOk;
-  for (PhaseTimer* t : {&t_all, &t_lz, &t_f, &t_qr, &t_rr})
-    if ((st = t->init())) return st;
-  auto cleanup = [&]() {
-    for (PhaseTimer* t : {&t_all, &t_lz, &t_f, &t_qr, &t_rr}) t->destroy();
-  };
-  auto fail = [&](int code) {
-    cleanup();
-    return code;
-  };
-
-  t_all.start(s);
-  if (!use_v0) {
-    if ((st = fill_gaussian(V, ldv, N, ne, P.seed, s))) return fail(st);
+  ProblemState ps;
+  ps.w = &h->w;
+  ps.P = h->p;
+  ps.A = reinterpret_cast<const z64*>(A_);
+  ps.lda = lda;
+  ps.V = reinterpret_cast<z64*>(V_);
+  ps.ldv = ldv;
+  PhaseTimer t_all;
+  if ((st = t_all.init()) || (st = ps.init_timers())) {
+    t_all.destroy();
+    ps.destroy_timers();
+    return st;
   }
-  // ---- Lanczos bounds (Alg. 2, first line)
-  double bnd[4];
-  int64_t total_mv = 0;
-  if (P.bounds_given) {
-    bnd[0] = P.b_sup;
-    bnd[1] = P.mu_1;
-    bnd[2] = P.mu_ne;
-    bnd[3] = P.norm_est;
-  } else {
-    const z64* starts = reinterpret_cast<const z64*>(starts_);
-    int64_t lds = ld_starts;
-    int ns = nstarts;
-    if (!starts) {
-      if ((st = fill_gaussian(w.starts, N, N, 4, P.seed ^ 0x5DEECE66Dull, s))) return fail(st);
-      starts = w.starts;
-      lds = N;
-      ns = 4;
+  auto run = [&]() -> int {
+    int r;
+    t_all.start(s);
+    if ((r = ps.setup(use_v0, reinterpret_cast<const z64*>(starts_), ld_starts, nstarts, s))) return r;
+    while (ps.active()) {
+      if ((r = ps.prepare(s))) return r;
+      if ((r = ps.filter_eager(s))) return r;
+      if ((r = ps.post_filter(s))) return r;
     }
-    t_lz.start(s);
-    if ((st = lanczos(w, A, lda, starts, lds, ns, P.lanczos_steps, ne, bnd, s))) return fail(st);
-    t_lz.stop(s);
-    total_mv += (int64_t)ns * std::min<int64_t>(P.lanczos_steps, N);
-  }
-  const double b_sup = bnd[0];
-  double mu_1 = bnd[1], mu_ne = bnd[2];
-  const double tol_abs = P.tol * bnd[3];
-
-  // mixed precision: FP32 copy of H
-  if (mixed) {
-    if ((st = convert_z_to_c(A, lda, w.A32, N, N, N, s))) return fail(st);
-  }
-
-  std::vector<int32_t> degs(ne, P.deg);
-  std::vector<double> Lam(ne, 0.0), resd(ne, std::numeric_limits<double>::infinity());
-  std::vector<char> low(ne, mixed ? 1 : 0);  // column still filtered in FP32
-  std::vector<double> prev_resd(ne, std::numeric_limits<double>::infinity());
-  int locked = 0, it = 1;
-  double c = 0.5 * (b_sup + mu_ne), e = 0.5 * (b_sup - mu_ne);
-  double mu1_cur = mu_1;
-  const double sw_abs = P.mixed_switch * bnd[3];
-
-  // C2 <- V (Alg. 2 keeps the saved copy; its active part is rewritten before use)
-  if ((st = copy_columns(V, ldv, w.C2, N, N, ne, s))) return fail(st);
-
-  std::vector<double> th_h(ne), rs_h(ne);
-  bool breakdown = false;
-  while (locked < nev && it <= P.max_iter) {
-    const int na = ne - locked;
-    if (it != 1) {
-      mu1_cur = *std::min_element(Lam.begin(), Lam.end());
-      mu_ne = *std::max_element(Lam.begin(), Lam.end());
-      c = 0.5 * (b_sup + mu_ne);
-      e = 0.5 * (b_sup - mu_ne);
-      if (P.opt)
-        for (int j = locked; j < ne; ++j)
-          degs[j] = degree_opt(resd[j], Lam[j], c, e, tol_abs, P.max_deg, P.deg_extra);
-      // stable sort of the active columns by (precision group, degree)
-      std::vector<int> order(na);
-      std::iota(order.begin(), order.end(), 0);
-      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        if (mixed && low[locked + x] != low[locked + y]) return low[locked + x] > low[locked + y];
-        return degs[locked + x] < degs[locked + y];
-      });
-      bool ident = true;
-      for (int j = 0; j < na; ++j) ident = ident && order[j] == j;
-      if (!ident) {
-        if ((st = apply_perm(w, V + (int64_t)locked * ldv, ldv, order, false, 0, s))) return fail(st);
-        auto permute = [&](auto& arr) {
-          auto tmp = arr;
-          for (int j = 0; j < na; ++j) arr[locked + j] = tmp[locked + order[j]];
-        };
-        permute(Lam);
-        permute(resd);
-        permute(degs);
-        permute(low);
-        permute(prev_resd);
-      }
-    }
-
-    // ---- Filter on the active columns
-    t_f.start(s);
-    int64_t mv = 0, nl = 0;
-    if (mixed) {
-      int nlow = 0;
-      while (nlow < na && low[locked + nlow]) ++nlow;
-      int64_t mv32 = 0, nl32 = 0;
-      if (nlow > 0) {
-        if ((st = run_filter_fp32(w.A32, N, V + (int64_t)locked * ldv, ldv, w.X32a, w.X32b, nlow,
-                                  degs.data() + locked, c, e, mu1_cur, &mv32, &nl32, s)))
-          return fail(st);
-      }
-      if (na - nlow > 0) {
-        if ((st = run_filter(A, lda, V + (int64_t)(locked + nlow) * ldv, ldv, w.B + (int64_t)(locked + nlow) * N, N, N,
-                             na - nlow, degs.data() + locked + nlow, c, e, mu1_cur, &mv, &nl, s)))
-          return fail(st);
-      }
-      S.filter_matvecs_fp32 += mv32;
-      mv += mv32;
-      nl += nl32;
-    } else {
-      if ((st = run_filter(A, lda, V + (int64_t)locked * ldv, ldv, w.B + (int64_t)locked * N, N, N, na,
-                           degs.data() + locked, c, e, mu1_cur, &mv, &nl, s)))
-        return fail(st);
-    }
-    t_f.stop(s);
-    S.filter_matvecs += mv;
-    S.filter_launches += nl;
-    total_mv += mv;
-
-    // ---- CondEst and 1D-CAQR on all n_e columns
-    std::vector<double> Lam_est = Lam;
-    if (it == 1) std::fill(Lam_est.begin(), Lam_est.end(), mu1_cur);
-    const double cond = cond_est(Lam_est.data(), c, e, degs.data(), ne, locked);
-    t_qr.start(s);
-    int variant = 0;
-    if ((st = caqr(w, V, ldv, ne, cond, P.force_qr, &variant, s))) return fail(st);
-    t_qr.stop(s);
-    S.qr_count[variant] += 1;
-
-    // ---- restore locked columns, save the new active ones
-    if (locked > 0 && (st = copy_columns(w.C2, N, V, ldv, N, locked, s))) return fail(st);
-    if ((st = copy_columns(V + (int64_t)locked * ldv, ldv, w.C2 + (int64_t)locked * N, N, N, na, s)))
-      return fail(st);
-
-    // ---- Rayleigh-Ritz and residuals
-    t_rr.start(s);
-    if ((st = rayleigh_ritz(w, A, lda, w.C2 + (int64_t)locked * N, N, V + (int64_t)locked * ldv, ldv, na, s)))
-      return fail(st);
-    t_rr.stop(s);
-    total_mv += 2 * (int64_t)na;
-    CHASE_CHK(hipMemcpyAsync(th_h.data(), w.theta, na * sizeof(double), hipMemcpyDeviceToHost, s));
-    CHASE_CHK(hipMemcpyAsync(rs_h.data(), w.resd, na * sizeof(double), hipMemcpyDeviceToHost, s));
+    if ((r = ps.finish(ritzv, resid, s))) return r;
+    t_all.stop(s);
     CHASE_CHK(hipStreamSynchronize(s));
-    for (PhaseTimer* t : {&t_lz, &t_f, &t_qr, &t_rr}) t->collect();
-    for (int j = 0; j < na; ++j) {
-      Lam[locked + j] = th_h[j];
-      prev_resd[locked + j] = resd[locked + j];
-      resd[locked + j] = rs_h[j];
-      if (!std::isfinite(th_h[j]) || !std::isfinite(rs_h[j])) breakdown = true;
-    }
-    if (breakdown) break;
-    if (mixed) {  // switch a column to FP64 once FP32 stops paying
-      for (int j = locked; j < ne; ++j)
-        if (low[j] && (resd[j] <= sw_abs || resd[j] > 0.5 * prev_resd[j])) low[j] = 0;
-    }
+    t_all.collect();
+    return kOk;
+  };
+  st = run();
+  ps.S.t_total = t_all.acc;
+  t_all.destroy();
+  ps.destroy_timers();
+  if (st) return st;
+  if (stats) *stats = ps.S;
+  return ps.S.status;
+}
 
-    // ---- Deflation and locking
-    std::vector<int> order;
-    std::vector<char> taken(na, 0);
-    int n_new = 0;
-    for (int j = 0; j < std::min(nev - locked, na); ++j)
-      if (resd[locked + j] <= tol_abs) {
-        order.push_back(j);
-        taken[j] = 1;
-        ++n_new;
-      }
-    for (int j = 0; j < na; ++j)
-      if (!taken[j]) order.push_back(j);
-    if (n_new > 0) {
-      bool ident = true;
-      for (int j = 0; j < na; ++j) ident = ident && order[j] == j;
-      if (!ident) {
-        if ((st = apply_perm(w, V + (int64_t)locked * ldv, ldv, order, true, locked, s))) return fail(st);
-        auto permute = [&](auto& arr) {
-          auto tmp = arr;
-          for (int j = 0; j < na; ++j) arr[locked + j] = tmp[locked + order[j]];
-        };
-        permute(Lam);
-        permute(resd);
-        permute(degs);
-        permute(low);
-        permute(prev_resd);
+int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As, const int64_t* ldas,
+                        void* const* Vs, const int64_t* ldvs, const int32_t* use_v0, const void* const* starts,
+                        const int64_t* ld_starts, const int32_t* nstarts, const chase_params_t* params,
+                        double* const* ritzv, double* const* resid, chase_stats_t* stats, chase_stream_t stream_) {
+  if (count < 1) return -1;
+  if (!Ns) return -2;
+  if (!As) return -3;
+  if (!ldas) return -4;
+  if (!Vs) return -5;
+  if (!ldvs) return -6;
+  if (!params) return -11;
+  if (!ritzv) return -12;
+  if (!resid) return -13;
+  for (int i = 0; i < count; ++i) {
+    if (Ns[i] < 2) return -2;
+    if (!valid_params(&params[i]) || (int64_t)params[i].nev + params[i].nex >= Ns[i]) return -11;
+    if (params[i].precision != CHASE_FP64) return -11;  // grouped filter is FP64
+    const void* st_i = starts ? starts[i] : nullptr;
+    const int64_t lds_i = (st_i && ld_starts) ? ld_starts[i] : 0;
+    const int32_t ns_i = (st_i && nstarts) ? nstarts[i] : 0;
+    int a = check_solve_args(Ns[i], As[i], ldas[i], Vs[i], ldvs[i], st_i, lds_i, ns_i, ritzv[i], resid[i]);
+    if (a) {
+      const int map[] = {0, 0, -3, -4, -5, -6, 0, -8, -9, -10, -12, -13};
+      return map[-a] ? map[-a] : a;
+    }
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+  std::vector<Workspace> ws(count);
+  std::vector<ProblemState> ps(count);
+  GroupEntry* h_table = nullptr;
+  GroupEntry* d_table = nullptr;
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  PhaseTimer t_all, t_f;
+  int max_deg = 2;
+  for (int i = 0; i < count; ++i) max_deg = std::max(max_deg, (int)std::max(params[i].max_deg, params[i].deg));
+
+  auto run = [&]() -> int {
+    int st;
+    if ((st = t_all.init()) || (st = t_f.init())) return st;
+    for (int i = 0; i < count; ++i) {
+      if ((st = ws[i].create(Ns[i], params[i].nev + params[i].nex, false, true))) return st;
+      ps[i].w = &ws[i];
+      ps[i].P = params[i];
+      ps[i].A = reinterpret_cast<const z64*>(As[i]);
+      ps[i].lda = ldas[i];
+      ps[i].V = reinterpret_cast<z64*>(Vs[i]);
+      ps[i].ldv = ldvs[i];
+      if ((st = ps[i].init_timers())) return st;
+    }
+    // Descriptor table: max_deg steps x count problems, pinned on the host.
+    const size_t tbytes = sizeof(GroupEntry) * (size_t)max_deg * count;
+    CHASE_CHK(hipHostMalloc(reinterpret_cast<void**>(&h_table), tbytes, hipHostMallocDefault));
+    CHASE_CHK(hipMalloc(reinterpret_cast<void**>(&d_table), tbytes));
+    int dev = 0, cus = 256;
+    CHASE_CHK(hipGetDevice(&dev));
+    CHASE_CHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int grid = (int)(8 * cdiv(cus, 8));
+    // One captured graph holds every degree step of the grouped filter; its
+    // kernels read all parameters from d_table, so it is replayed unchanged.
+    CHASE_CHK(hipStreamCreate(&cs));
+    CHASE_CHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < max_deg; ++k) {
+      if ((st = zfilter_grouped_launch(d_table, count, k, grid, cs))) {
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(cs, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+        return st;
       }
     }
-    locked += n_new;
-    ++it;
-  }
+    CHASE_CHK(hipStreamEndCapture(cs, &graph));
+    CHASE_CHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
 
-  // ---- output: ascending eigenvalues in V[:, 0:nev]
-  const bool converged = locked >= nev;
-  std::vector<int> idx(converged ? locked : ne);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return Lam[x] < Lam[y]; });
-  idx.resize(nev);
-  if ((st = apply_perm(w, V, ldv, std::vector<int>(idx.begin(), idx.end()), false, 0, s))) return fail(st);
-  for (int j = 0; j < nev; ++j) {
-    ritzv[j] = Lam[idx[j]];
-    resid[j] = resd[idx[j]];
+    t_all.start(s);
+    for (int i = 0; i < count; ++i) {
+      const void* st_i = starts ? starts[i] : nullptr;
+      if ((st = ps[i].setup(use_v0 ? use_v0[i] : 1, reinterpret_cast<const z64*>(st_i),
+                            st_i && ld_starts ? ld_starts[i] : 0, st_i && nstarts ? nstarts[i] : 0, s)))
+        return st;
+    }
+    while (true) {
+      bool any = false;
+      for (int i = 0; i < count; ++i) any = any || ps[i].active();
+      if (!any) break;
+      std::memset(h_table, 0, tbytes);
+      for (int i = 0; i < count; ++i) {
+        if (!ps[i].active()) continue;
+        if ((st = ps[i].prepare(s))) return st;
+        const std::vector<GemmArgs> steps = ps[i].plan();
+        if ((int)steps.size() > max_deg) return -11;
+        int64_t mv = 0;
+        for (size_t k = 0; k < steps.size(); ++k) {
+          GroupEntry& e = h_table[k * count + i];
+          e.g = steps[k];
+          zfilter_tiles(steps[k].M, steps[k].N, &e.tiles_n);
+          mv += steps[k].N;
+        }
+        ps[i].S.filter_matvecs += mv;
+        ps[i].S.filter_launches += (int64_t)steps.size();
+        ps[i].total_mv += mv;
+      }
+      for (int k = 0; k < max_deg; ++k) {  // running tile counts per step
+        int64_t acc = 0;
+        for (int i = 0; i < count; ++i) {
+          GroupEntry& e = h_table[(size_t)k * count + i];
+          acc += zfilter_tiles(e.g.M, e.g.N, nullptr);
+          e.tile_end = acc;
+        }
+      }
+      CHASE_CHK(hipMemcpyAsync(d_table, h_table, tbytes, hipMemcpyHostToDevice, s));
+      t_f.start(s);
+      CHASE_CHK(hipGraphLaunch(exec, s));
+      t_f.stop(s);
+      for (int i = 0; i < count; ++i) {
+        if (!ps[i].active()) continue;
+        if ((st = ps[i].post_filter(s))) return st;  // synchronises s: h_table may be rewritten
+      }
+      t_f.collect();
+    }
+    for (int i = 0; i < count; ++i)
+      if ((st = ps[i].finish(ritzv[i], resid[i], s))) return st;
+    t_all.stop(s);
+    CHASE_CHK(hipStreamSynchronize(s));
+    t_all.collect();
+    return kOk;
+  };
+  int st = run();
+  (void)hipStreamSynchronize(s);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (d_table) (void)hipFree(d_table);
+  if (h_table) (void)hipHostFree(h_table);
+  int worst = kOk;
+  for (int i = 0; i < count; ++i) {
+    if (!st && stats) {
+      stats[i] = ps[i].S;
+      stats[i].t_total = t_all.acc;
+      stats[i].t_filter = t_f.acc;  // the grouped filter is shared by all problems
+    }
+    if (!st && ps[i].S.status > worst) worst = ps[i].S.status;
+    ps[i].destroy_timers();
+    ws[i].release();
   }
-  t_all.stop(s);
-  CHASE_CHK(hipStreamSynchronize(s));
-  for (PhaseTimer* t : {&t_all, &t_lz, &t_f, &t_qr, &t_rr}) t->collect();
-  S.status = breakdown ? kBreakdown : (converged ? kOk : kNotConverged);
-  S.iterations = it - 1;
-  S.locked = locked;
-  S.total_matvecs = total_mv;
-  S.filter_flops = 8.0 * (double)N * (double)N * (double)S.filter_matvecs;
-  S.t_total = t_all.acc;
-  S.t_lanczos = t_lz.acc;
-  S.t_filter = t_f.acc;
-  S.t_qr = t_qr.acc;
-  S.t_rr = t_rr.acc;
-  S.t_resid = 0.0;  // fused into the Rayleigh-Ritz phase (reassociated H V)
-  for (int i = 0; i < 4; ++i) S.bounds[i] = bnd[i];
-  if (stats) *stats = S;
-  cleanup();
-  return S.status;
+  t_all.destroy();
+  t_f.destroy();
+  return st ? st : worst;
 }
 
 int chase_eigval_grad(int64_t N, int32_t nev, const void* X, int64_t ldx, const double* g, void* G, int64_t ldg,
@@ -964,11 +1193,27 @@ int chase_filter(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int6
     if (degs[j] < 2 || degs[j] % 2 || (j > 0 && degs[j] < degs[j - 1])) return -9;
   if (!(e > 0)) return -11;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  void* tws = nullptr;
+  int* tcnt = nullptr;
+  if (hipMalloc(&tws, (size_t)tail_workspace_bytes()) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&tcnt), sizeof(int) * kTailMaxSegments) != hipSuccess) {
+    (void)hipGetLastError();
+    if (tws) (void)hipFree(tws);
+    return kAllocFailed;
+  }
   int64_t mv = 0, nl = 0;
-  int st = run_filter(reinterpret_cast<const z64*>(A), lda, reinterpret_cast<z64*>(V), ldv,
-                      reinterpret_cast<z64*>(W), ldw, N, n, degs, c, e, mu_1, &mv, &nl, s);
+  int st = tail_counters_init(tcnt, s);
+  if (!st)
+    st = run_filter(reinterpret_cast<const z64*>(A), lda, reinterpret_cast<z64*>(V), ldv,
+                    reinterpret_cast<z64*>(W), ldw, N, n, degs, c, e, mu_1, &mv, &nl, s, tws, tcnt);
+  hipError_t err = hipStreamSynchronize(s);
+  (void)hipFree(tws);
+  (void)hipFree(tcnt);
   if (st) return st;
-  CHASE_CHK(hipStreamSynchronize(s));
+  if (err != hipSuccess) {
+    set_last_error("chase_filter", err);
+    return kHipError;
+  }
   if (matvecs) *matvecs = mv;
   return kOk;
 }

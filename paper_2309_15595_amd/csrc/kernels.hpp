@@ -21,9 +21,33 @@ struct GemmArgs {
 
 // opa/opb: 0 = as stored, 1 = conjugate transpose.
 int zgemm_launch(int opa, int opb, const GemmArgs& g, hipStream_t s, bool filter_symbol = false);
+// Split of the last, partial round of tiles along K (see zfilter.hip).
+constexpr int kTailMaxSegments = 1024;
+struct TailSplit {
+  int64_t full = 0;        // tiles computed whole, one workgroup each
+  int64_t ksplit = 1;      // K segments per remaining tile
+  void* ws = nullptr;      // kTailMaxSegments partial tiles
+  int* counters = nullptr; // kTailMaxSegments arrival counters, zero between launches
+};
+int64_t tail_workspace_bytes();
+int tail_counters_init(int* counters, hipStream_t s);
 // Large NN products (filter step, H C): 128 x 128 tiles, double-buffered LDS
 // (zfilter.hip).  filter_symbol selects the kernel name reported by profilers.
-int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol);
+// With a tail workspace the last partial round of tiles is split along K.
+int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws = nullptr,
+                        int* tail_counters = nullptr);
+// One problem's filter GEMM in a grouped launch: tiles [tile_end - tiles,
+// tile_end) of the step's running tile count belong to it.
+struct GroupEntry {
+  GemmArgs g;
+  int64_t tiles_n = 1;
+  int64_t tile_end = 0;
+};
+// Tiles of the filter kernel for an M x N output (tiles_n: column tiles).
+int64_t zfilter_tiles(int64_t M, int64_t N, int64_t* tiles_n);
+// Persistent grouped filter step over row `step` of a device table of
+// `count` entries per step; grid a multiple of 8.
+int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s);
 // Split over K into `splits` partial products in `ws`, summed in fixed order;
 // hermitise = 1 stores (S + S^H)/2 (M == N).
 int zgemm_splitk(int opa, int opb, const GemmArgs& g, void* ws, int splits, int hermitise,

@@ -23,7 +23,7 @@
 #include "kernels.hpp"
 
 #ifndef ZF_CONFIG
-#define ZF_CONFIG 1
+#define ZF_CONFIG 4
 #endif
 
 namespace chase {
@@ -47,6 +47,7 @@ __device__ __forceinline__ bool map_tile(int64_t ntiles, int64_t tiles_n, int64_
 template <int WGM, int WGN, int TM, int TN, int BK>
 struct Cfg {
   static constexpr int NT = 64 * WGM * WGN;
+  static constexpr int BK_ = BK;
   static constexpr int BM = WGM * TM * 16;
   static constexpr int BN = WGN * TN * 16;
   static constexpr int APAD = BM + 2;
@@ -63,21 +64,31 @@ struct Smem {
   double b[2][2][BK][C::BPAD];  // [buffer][re/im][k][n]
 };
 
-template <int WGM, int WGN, int TM, int TN, int BK>
-__device__ __forceinline__ void zbig_body(const GemmArgs& g) {
+// One BM x BN output tile (tm, tn) of g.  EDGE tiles overhang the output:
+// MFMA blocks of a wave that lie wholly outside it are skipped (the padded
+// columns of the last column tile are most of its work when n_act is small).
+//
+// kbeg/kend (multiples of BK) restrict the K range; with part != nullptr the
+// raw accumulator tile is stored there (tile-local, m fastest) instead of
+// applying the epilogue.
+template <int WGM, int WGN, int TM, int TN, int BK, bool EDGE>
+__device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg,
+                                               int64_t kend, zv* part,
+                                               Smem<Cfg<WGM, WGN, TM, TN, BK>, BK>& s) {
   using C = Cfg<WGM, WGN, TM, TN, BK>;
   constexpr int NT = C::NT, BM = C::BM, BN = C::BN, LA = C::LA, LB = C::LB;
-  __shared__ Smem<C, BK> s;
-
-  const int64_t tiles_m = (g.M + BM - 1) / BM;
-  const int64_t tiles_n = (g.N + BN - 1) / BN;
-  int64_t tm, tn;
-  if (!map_tile(tiles_m * tiles_n, tiles_n, tm, tn)) return;
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int l16 = lane & 15, kq = lane >> 4;
+  // 16-blocks of this wave that touch the output (uniform across the wave)
+  int vmb = TM, vnb = TN;
+  if (EDGE) {
+    const int64_t rm = g.M - (m0 + wm * TM * 16), rn = g.N - (n0 + wn * TN * 16);
+    vmb = (int)(rm <= 0 ? 0 : (rm >= TM * 16 ? TM : (rm + 15) / 16));
+    vnb = (int)(rn <= 0 ? 0 : (rn >= TN * 16 ? TN : (rn + 15) / 16));
+  }
 
   f64x4 cr[TN][TM], ci[TN][TM];
 #pragma unroll
@@ -96,13 +107,13 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g) {
     for (int r = 0; r < LA; ++r) {
       const int e = t + NT * r;
       const int64_t m = m0 + (e % BM), k = k0 + (e / BM);
-      ra[r] = (m < g.M && k < g.K) ? A[m + k * g.lda] : zv{0.0, 0.0};
+      ra[r] = (m < g.M && k < kend) ? A[m + k * g.lda] : zv{0.0, 0.0};
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       const int e = t + NT * r;
       const int64_t k = k0 + (e % BK), n = n0 + (e / BK);
-      rb[r] = (n < g.N && k < g.K) ? B[k + n * g.ldb] : zv{0.0, 0.0};
+      rb[r] = (n < g.N && k < kend) ? B[k + n * g.ldb] : zv{0.0, 0.0};
     }
   };
   auto sstore = [&](int buf) {
@@ -120,11 +131,11 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g) {
     }
   };
 
-  const int64_t nkt = (g.K + BK - 1) / BK;
+  const int64_t nkt = (kend - kbeg + BK - 1) / BK;
   if (nkt > 0) {
-    gload(0);
+    gload(kbeg);
     sstore(0);
-    if (nkt > 1) gload(BK);
+    if (nkt > 1) gload(kbeg + BK);
   }
   __syncthreads();
   for (int64_t kt = 0; kt < nkt; ++kt) {
@@ -147,6 +158,7 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g) {
       for (int nb = 0; nb < TN; ++nb)
 #pragma unroll
         for (int mb = 0; mb < TM; ++mb) {
+          if (EDGE && (nb >= vnb || mb >= vmb)) continue;
           cr[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[nb], ar[mb], cr[nb][mb], 0, 0, 0);
           ci[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[nb], ai[mb], ci[nb][mb], 0, 0, 0);
         }
@@ -154,17 +166,31 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g) {
       for (int nb = 0; nb < TN; ++nb)
 #pragma unroll
         for (int mb = 0; mb < TM; ++mb) {
+          if (EDGE && (nb >= vnb || mb >= vmb)) continue;
           cr[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi[nb], ai[mb], cr[nb][mb], 0, 0, 0);
           ci[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[nb], ar[mb], ci[nb][mb], 0, 0, 0);
         }
     }
     if (kt + 1 < nkt) {
       sstore(buf ^ 1);
-      if (kt + 2 < nkt) gload((kt + 2) * BK);
+      if (kt + 2 < nkt) gload(kbeg + (kt + 2) * BK);
     }
     __syncthreads();
   }
 
+  if (part != nullptr) {
+#pragma unroll
+    for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+      for (int mb = 0; mb < TM; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int nl = wn * TN * 16 + nb * 16 + kq + 4 * r;
+          const int ml = wm * TM * 16 + mb * 16 + l16;
+          part[ml + nl * BM] = zv{cr[nb][mb][r], ci[nb][mb][r]};
+        }
+    return;
+  }
   zv* Y = reinterpret_cast<zv*>(g.Y);
   const zv* Z = reinterpret_cast<const zv*>(g.Z);
 #pragma unroll
@@ -191,6 +217,111 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g) {
       }
 }
 
+template <int WGM, int WGN, int TM, int TN, int BK>
+__device__ __forceinline__ void zbig_tile(const GemmArgs& g, int64_t tm, int64_t tn,
+                                          Smem<Cfg<WGM, WGN, TM, TN, BK>, BK>& s, int64_t kbeg = 0,
+                                          int64_t kend = -1, zv* part = nullptr) {
+  using C = Cfg<WGM, WGN, TM, TN, BK>;
+  if (kend < 0) kend = g.K;
+  if ((tm + 1) * C::BM <= g.M && (tn + 1) * C::BN <= g.N)
+    zbig_tile_impl<WGM, WGN, TM, TN, BK, false>(g, tm, tn, kbeg, kend, part, s);
+  else
+    zbig_tile_impl<WGM, WGN, TM, TN, BK, true>(g, tm, tn, kbeg, kend, part, s);
+}
+
+// Whole launch: tiles [0, tail.full) one per workgroup (XCD-major), then
+// the remaining tiles of the last, partial round split along K into
+// tail.ksplit segments.  A segment stores its partial accumulator and
+// counts itself in; the last segment of a tile to arrive sums the partials
+// in segment order (deterministic), applies the epilogue and resets the
+// counter for the next launch.  No workgroup ever waits on another.
+template <int WGM, int WGN, int TM, int TN, int BK>
+__device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& tail) {
+  using C = Cfg<WGM, WGN, TM, TN, BK>;
+  constexpr int BM = C::BM, BN = C::BN;
+  __shared__ Smem<C, BK> s;
+  __shared__ int last;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t grid_main = 8 * ((tail.full + 7) / 8);
+  if ((int64_t)blockIdx.x < grid_main) {
+    int64_t tm, tn;
+    if (!map_tile(tail.full, tiles_n, tm, tn)) return;
+    zbig_tile<WGM, WGN, TM, TN, BK>(g, tm, tn, s);
+    return;
+  }
+  const int64_t j = (int64_t)blockIdx.x - grid_main;       // tail segment
+  const int64_t tl = j / tail.ksplit, sp = j % tail.ksplit;  // tail tile, split
+  const int64_t tile = tail.full + tl;
+  const int64_t tm = tile / tiles_n, tn = tile % tiles_n;
+  const int64_t nkt = (g.K + BK - 1) / BK;
+  const int64_t per = (nkt + tail.ksplit - 1) / tail.ksplit;
+  const int64_t kbeg = sp * per * BK;
+  const int64_t kend = (sp + 1) * per * BK < g.K ? (sp + 1) * per * BK : g.K;
+  zv* part = reinterpret_cast<zv*>(tail.ws) + j * (int64_t)(BM * BN);
+  zbig_tile<WGM, WGN, TM, TN, BK>(g, tm, tn, s, kbeg, kend, part);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(tail.counters + tl, 1) == tail.ksplit - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const zv* parts = reinterpret_cast<const zv*>(tail.ws) + tl * tail.ksplit * (int64_t)(BM * BN);
+  zv* Y = reinterpret_cast<zv*>(g.Y);
+  const zv* Z = reinterpret_cast<const zv*>(g.Z);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  for (int e = threadIdx.x; e < BM * BN; e += C::NT) {
+    const int64_t m = m0 + e % BM, n = n0 + e / BM;
+    if (m >= g.M || n >= g.N) continue;
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < tail.ksplit; ++q) {
+      const zv v = parts[q * (int64_t)(BM * BN) + e];
+      sr += v.re;
+      si += v.im;
+    }
+    zv out{g.alpha * sr, g.alpha * si};
+    if (g.beta != 0.0) {
+      const zv y = Y[m + n * g.ldy];
+      out.re += g.beta * y.re;
+      out.im += g.beta * y.im;
+    }
+    if (g.gamma != 0.0) {
+      const zv z = Z[m + n * g.ldz];
+      out.re += g.gamma * z.re;
+      out.im += g.gamma * z.im;
+    }
+    Y[m + n * g.ldy] = out;
+  }
+  if (threadIdx.x == 0) tail.counters[tl] = 0;
+}
+
+// Grouped, persistent form for many problems at once: row `step` of the
+// descriptor table lists one GEMM per problem with its tile count as a running
+// prefix sum.  A fixed grid (a multiple of 8 workgroups) walks the tiles
+// XCD-major; every parameter comes from device memory, so a captured graph
+// of these launches stays valid while degrees, columns and scalars change.
+template <int WGM, int WGN, int TM, int TN, int BK>
+__device__ __forceinline__ void zbig_grouped(const GroupEntry* __restrict__ table, int count, int step) {
+  using C = Cfg<WGM, WGN, TM, TN, BK>;
+  __shared__ Smem<C, BK> s;
+  const GroupEntry* __restrict__ row = table + (int64_t)step * count;
+  const int64_t total = row[count - 1].tile_end;
+  if (total <= 0) return;
+  const int64_t xcd = blockIdx.x % 8, slot = blockIdx.x / 8, slots = gridDim.x / 8;
+  const int64_t per = (total + 7) / 8;
+  int p = 0;
+  for (int64_t i = slot; i < per; i += slots) {
+    const int64_t t = xcd * per + i;
+    if (t >= total) break;
+    while (row[p].tile_end <= t) ++p;   // tiles are visited in increasing order
+    p = __builtin_amdgcn_readfirstlane(p);  // uniform: entry fields go to SGPRs
+    const int64_t begin = p > 0 ? row[p - 1].tile_end : 0;
+    const int64_t lt = t - begin;
+    const GemmArgs g = row[p].g;
+    const int64_t tiles_n = row[p].tiles_n;
+    zbig_tile<WGM, WGN, TM, TN, BK>(g, lt / tiles_n, lt % tiles_n, s);
+  }
+}
+
 // Configuration: (waves along m, waves along n, 16-blocks per wave m, n, K tile)
 #if ZF_CONFIG == 1
 #define ZF_ARGS 2, 4, 4, 2, 16   // 128 x 128 tile, 8 waves of 64 x 32
@@ -204,23 +335,89 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g) {
 
 using ZC = Cfg<ZF_ARGS>;
 
-__global__ __launch_bounds__(ZC::NT, 1) void zfilter_step(GemmArgs g) { zbig_body<ZF_ARGS>(g); }
+__global__ __launch_bounds__(ZC::NT, 1) void zfilter_step(GemmArgs g, TailSplit t) { zbig_body<ZF_ARGS>(g, t); }
 // Same schedule for the other large H-times-block products (Rayleigh-Ritz H C).
-__global__ __launch_bounds__(ZC::NT, 1) void zgemm_nn_big(GemmArgs g) { zbig_body<ZF_ARGS>(g); }
+__global__ __launch_bounds__(ZC::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit t) { zbig_body<ZF_ARGS>(g, t); }
+__global__ void counters_zero(int* c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = 0;
+}
+__global__ __launch_bounds__(ZC::NT, 1) void zfilter_grouped(const GroupEntry* __restrict__ table, int count, int step) {
+  zbig_grouped<ZF_ARGS>(table, count, step);
+}
 
 }  // namespace
 
-int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol) {
+int64_t zfilter_tiles(int64_t M, int64_t N, int64_t* tiles_n) {
+  if (tiles_n) *tiles_n = cdiv(N, ZC::BN);
+  if (M <= 0 || N <= 0) return 0;
+  return cdiv(M, ZC::BM) * cdiv(N, ZC::BN);
+}
+
+int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s) {
+  if (count <= 0 || grid <= 0 || grid % 8) return -1;
+  hipLaunchKernelGGL(zfilter_grouped, dim3((unsigned)grid), dim3(ZC::NT), 0, s, table, count, step);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+static int cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+int64_t tail_workspace_bytes() { return (int64_t)kTailMaxSegments * ZC::BM * ZC::BN * 16; }
+
+int tail_counters_init(int* counters, hipStream_t s) {
+  hipLaunchKernelGGL(counters_zero, dim3((kTailMaxSegments + 255) / 256), dim3(256), 0, s, counters,
+                     kTailMaxSegments);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws, int* tail_counters) {
   if (g.M <= 0 || g.N <= 0) return kOk;
   if (g.ws != nullptr || g.upper_b || g.lower_only || g.bscale != nullptr) return -1;
   const int64_t tiles = cdiv(g.M, ZC::BM) * cdiv(g.N, ZC::BN);
-  const dim3 grid((unsigned)(8 * cdiv(tiles, 8)));
+  const int64_t G = cu_count();  // one workgroup per CU (LDS and registers)
+  TailSplit t;
+  t.full = tiles;
+  t.ksplit = 1;
+  t.ws = tail_ws;
+  t.counters = tail_counters;
+  const int64_t nkt = cdiv(g.K, ZC::BK_);
+  const int64_t rem = tiles % G;
+  if (tail_ws && tail_counters && rem > 0) {
+    // split the last round's tiles along K to fill the idle CUs: minimise
+    // ceil(rem * s / G) / s (in units of one tile's time)
+    int best = 1;
+    double cost_best = 1.0;
+    for (int sp = 2; sp <= 8; ++sp) {
+      if (nkt < 16 * sp || rem * sp > kTailMaxSegments) break;
+      const double cost = (double)cdiv(rem * sp, G) / sp;
+      if (cost < cost_best - 1e-9) {
+        cost_best = cost;
+        best = sp;
+      }
+    }
+    if (best > 1) {
+      t.full = tiles - rem;
+      t.ksplit = best;
+    }
+  }
+  const int64_t grid = 8 * cdiv(t.full, 8) + (tiles - t.full) * t.ksplit;
   GemmArgs a = g;
   if (a.K <= 0) a.alpha = 0.0;
   if (filter_symbol)
-    hipLaunchKernelGGL(zfilter_step, grid, dim3(ZC::NT), 0, s, a);
+    hipLaunchKernelGGL(zfilter_step, dim3((unsigned)grid), dim3(ZC::NT), 0, s, a, t);
   else
-    hipLaunchKernelGGL(zgemm_nn_big, grid, dim3(ZC::NT), 0, s, a);
+    hipLaunchKernelGGL(zgemm_nn_big, dim3((unsigned)grid), dim3(ZC::NT), 0, s, a, t);
   CHASE_CHK_LAUNCH();
   return kOk;
 }

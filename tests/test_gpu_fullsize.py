@@ -1,0 +1,130 @@
+"""GPU checks at the workloads' full sizes, in the configuration bench.py
+times.  The oracle cannot solve these; they are checked against properties
+that hold at any size (the prescribed spectrum, residual and orthogonality
+bounds), against single-problem solves, and on sampled outputs the CPU
+computes one by one."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth import problems as sp
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_15595_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _solve(L, A, V0, S, nev, nex, **kw):
+    from paper_2309_15595_amd.api import Solver
+    V = V0.clone()
+    with Solver(A.shape[0], nev, nex, **kw) as s:
+        ritz, resid, info = s.solve_colmajor(A, V, True, S)
+    return ritz, resid, info, V
+
+
+def _ortho(V, nev):
+    X = V[:nev]
+    G = X.conj() @ X.T
+    return float(torch.linalg.matrix_norm(G - torch.eye(nev, dtype=G.dtype, device=G.device), ord=2))
+
+
+def test_dft_20000_fp64_and_mixed(L):
+    """N = 20000, nev 1000, nex 300: FP64 and FP32-mixed solves both reach
+    the prescribed spectrum to 1e-10 ||H||; per-eigenpair error of the mixed
+    result against the FP64 one is reported."""
+    N, nev, nex = 20000, 1000, 300
+    lam = synth.dft_like_spectrum(N)
+    A = sp.hermitian_from_spectrum_torch(lam, seed=sp.SEED_Q, device="cuda")
+    V0 = torch.from_numpy(np.ascontiguousarray(
+        synth.complex_gaussian(np.random.default_rng(sp.SEED_V0), (N, nev + nex)).T)).cuda()
+    S = torch.from_numpy(np.ascontiguousarray(
+        synth.complex_gaussian(np.random.default_rng(sp.SEED_LANCZOS), (N, 4)).T)).cuda()
+    normA = float(np.max(np.abs(lam)))
+    r64, res64, info64, V64 = _solve(L, A, V0, S, nev, nex)
+    assert info64.converged
+    assert np.max(np.abs(r64 - lam[:nev])) <= 1e-10 * normA
+    assert np.max(res64) <= 1e-10 * normA
+    assert _ortho(V64, nev) <= 1e-12
+    # sampled residuals recomputed with torch's own GEMV (the solved matrix is conj(A))
+    for j in (0, nev // 2, nev - 1):
+        x = V64[j]
+        r = torch.conj(A @ torch.conj(x)) - r64[j] * x
+        assert float(torch.linalg.vector_norm(r)) <= 1e-10 * normA
+    r32, res32, info32, V32 = _solve(L, A, V0, S, nev, nex, precision=L.CHASE_FP32_MIXED)
+    assert info32.converged
+    err = np.abs(r32 - r64) / normA
+    print(f"\nmixed vs FP64: max |d lambda|/||A|| = {err.max():.2e}, median {np.median(err):.2e}; "
+          f"times {info64.stats['t_total']:.2f} s FP64, {info32.stats['t_total']:.2f} s mixed; "
+          f"FP32 MatVec share {info32.stats['filter_matvecs_fp32'] / info32.stats['filter_matvecs']:.2f}")
+    assert err.max() <= 1e-10
+    assert np.max(np.abs(r32 - lam[:nev])) <= 1e-10 * normA
+    assert _ortho(V32, nev) <= 1e-12
+
+
+def test_batched_64_problems(L):
+    """64 problems, N ~ U[2000, 12000], nev = N/20, nex = N/80, DFT-like
+    spectra with per-problem seeds, one grouped solve."""
+    from paper_2309_15595_amd.api import solve_batched
+    Ns = np.random.default_rng(2309).integers(2000, 12001, 64)
+    A_cms, V_cms, S_cms, lams = [], [], [], []
+    for i, N in enumerate(Ns):
+        N = int(N)
+        lam = synth.dft_like_spectrum(N)
+        A = sp.hermitian_from_spectrum_torch(lam, seed=2309000 + i, device="cuda")
+        ne = N // 20 + N // 80
+        V = torch.from_numpy(np.ascontiguousarray(synth.complex_gaussian(
+            np.random.default_rng(2309100 + i), (N, ne)).T)).cuda()
+        S = torch.from_numpy(np.ascontiguousarray(synth.complex_gaussian(
+            np.random.default_rng(2309200 + i), (N, 4)).T)).cuda()
+        A_cms.append(A)
+        V_cms.append(V)
+        S_cms.append(S)
+        lams.append(lam)
+    V_init = [v.clone() for v in V_cms[:2]]
+    nevs = [int(N) // 20 for N in Ns]
+    nexs = [int(N) // 80 for N in Ns]
+    ritz, resid, stats, st = solve_batched(A_cms, V_cms, nevs, nexs, S_cms)
+    assert st == 0
+    t_total = stats[0]["t_total"]
+    for i in range(64):
+        normA = float(np.max(np.abs(lams[i])))
+        assert np.max(np.abs(ritz[i] - lams[i][: nevs[i]])) <= 1e-10 * normA, i
+        assert np.max(resid[i]) <= 1e-10 * normA, i
+    for i in (0, 1):
+        assert _ortho(V_cms[i], nevs[i]) <= 1e-12
+        r1, _, info1, _ = _solve(L, A_cms[i], V_init[i], S_cms[i], nevs[i], nexs[i])
+        assert np.max(np.abs(r1 - ritz[i])) <= 1e-13 * float(np.max(np.abs(lams[i])))
+    print(f"\nbatched 64 problems: {t_total:.2f} s, filter {stats[0]['t_filter']:.2f} s")
+
+
+def test_eigval_grad_50000_sampled(L):
+    """G = X diag(w) X^H at N = 50000, nev = 2000 (40 GB output), checked on
+    sampled entries computed one by one on the host."""
+    N, nev = 50000, 2000
+    rng = np.random.default_rng(2312)
+    X = torch.randn((nev, N), dtype=torch.complex128, device="cuda") / np.sqrt(N)
+    w = torch.from_numpy(sp.loss_weights(nev)).cuda()
+    G = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    L.chase_eigval_grad(N, nev, L.dptr(X), N, L.dptr(w), L.dptr(G), N, 0, L.stream_ptr())
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()            # (nev, N): row k is column k of X
+    wh = w.cpu().numpy()
+    rows = rng.integers(0, N, 40)
+    cols = rng.integers(0, N, 40)
+    Gs = G[rows, cols].cpu().numpy()   # G as stored column-major: entry (i, j) at G[j, i]
+    u = 2.0 ** -53
+    for a, (i, j) in enumerate(zip(rows, cols)):
+        terms = Xh[:, j] * wh * np.conj(Xh[:, i])     # column-major (j, i) entry
+        ref = np.sum(terms)
+        bound = 4 * nev * u * np.sum(np.abs(terms))   # summation-order error bound
+        assert abs(Gs[a] - ref) <= bound, (i, j, abs(Gs[a] - ref), bound)
