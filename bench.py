@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Chebyshev-filter TFLOP/s + time-to-solution at resid 1e-10, FP64 vs mixed"
 PEAK = {"f64": 78.6, "f32": 157.3}  # MI355X dense matrix TFLOP/s
-KERNEL_SRC = os.path.join(ROOT, "paper_2309_15595_amd", "csrc", "zgemm.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2309_15595_amd", "csrc", "zfilter.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zfilter_step_traffic.txt")
 
 

@@ -21,6 +21,7 @@
 #include <limits>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace chase {
@@ -1039,6 +1040,10 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   PhaseTimer t_all, t_f;
+  const int nw = std::min(count, 8);   // worker threads / streams for the per-problem steps
+  std::vector<hipStream_t> wstreams(nw, nullptr);
+  hipEvent_t filtered = nullptr;
+  int dev = 0;
   int max_deg = 2;
   for (int i = 0; i < count; ++i) max_deg = std::max(max_deg, (int)std::max(params[i].max_deg, params[i].deg));
 
@@ -1059,8 +1064,10 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
     const size_t tbytes = sizeof(GroupEntry) * (size_t)max_deg * count;
     CHASE_CHK(hipHostMalloc(reinterpret_cast<void**>(&h_table), tbytes, hipHostMallocDefault));
     CHASE_CHK(hipMalloc(reinterpret_cast<void**>(&d_table), tbytes));
-    int dev = 0, cus = 256;
+    int cus = 256;
     CHASE_CHK(hipGetDevice(&dev));
+    for (int wk = 0; wk < nw; ++wk) CHASE_CHK(hipStreamCreate(&wstreams[wk]));
+    CHASE_CHK(hipEventCreateWithFlags(&filtered, hipEventDisableTiming));
     CHASE_CHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int grid = (int)(8 * cdiv(cus, 8));
     // One captured graph holds every degree step of the grouped filter; its
@@ -1118,10 +1125,25 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
       t_f.start(s);
       CHASE_CHK(hipGraphLaunch(exec, s));
       t_f.stop(s);
-      for (int i = 0; i < count; ++i) {
-        if (!ps[i].active()) continue;
-        if ((st = ps[i].post_filter(s))) return st;  // synchronises s: h_table may be rewritten
-      }
+      CHASE_CHK(hipEventRecord(filtered, s));
+      // The rest of the iteration is per problem and latency-bound (small
+      // kernels, the eigensolve, host decisions): overlap problems on
+      // worker threads, each with its own stream after the grouped filter.
+      std::vector<int> wst(nw, kOk);
+      std::vector<std::thread> pool;
+      for (int wk = 0; wk < nw; ++wk)
+        pool.emplace_back([&, wk]() {
+          if (hipSetDevice(dev) != hipSuccess || hipStreamWaitEvent(wstreams[wk], filtered, 0) != hipSuccess) {
+            wst[wk] = kHipError;
+            return;
+          }
+          for (int i = wk; i < count; i += nw)
+            if (ps[i].active() && (wst[wk] = ps[i].post_filter(wstreams[wk]))) return;
+        });
+      for (auto& th : pool) th.join();
+      for (int wk = 0; wk < nw; ++wk)
+        if (wst[wk]) return wst[wk];
+      for (int wk = 0; wk < nw; ++wk) CHASE_CHK(hipStreamSynchronize(wstreams[wk]));
       t_f.collect();
     }
     for (int i = 0; i < count; ++i)
@@ -1136,6 +1158,9 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cs) (void)hipStreamDestroy(cs);
+  for (hipStream_t w : wstreams)
+    if (w) (void)hipStreamDestroy(w);
+  if (filtered) (void)hipEventDestroy(filtered);
   if (d_table) (void)hipFree(d_table);
   if (h_table) (void)hipHostFree(h_table);
   int worst = kOk;
