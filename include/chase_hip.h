@@ -66,7 +66,8 @@ typedef struct {
   int32_t lanczos_steps;/* steps per Lanczos run (25) */
   int32_t force_qr;     /* CHASE_QR_AUTO, or force one QR variant (testing) */
   int32_t bounds_given; /* 1 = skip Lanczos and use b_sup, mu_1, mu_ne, norm_est */
-  int32_t pad0;
+  int32_t autotune;     /* 1 = pick the filter's tile shape per size by timing the
+                           candidates (results kept for the process); 0 = default */
   double tol;           /* residual threshold relative to ||H|| (1e-10) */
   double b_sup, mu_1, mu_ne, norm_est;
   double mixed_switch;  /* FP32 -> FP64 switch at resd <= mixed_switch * ||H|| (1e-6) */

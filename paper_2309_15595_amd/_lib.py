@@ -25,7 +25,7 @@ class chase_params_t(C.Structure):
         ("nev", C.c_int32), ("nex", C.c_int32), ("deg", C.c_int32), ("max_deg", C.c_int32),
         ("deg_extra", C.c_int32), ("max_iter", C.c_int32), ("opt", C.c_int32),
         ("precision", C.c_int32), ("lanczos_steps", C.c_int32), ("force_qr", C.c_int32),
-        ("bounds_given", C.c_int32), ("pad0", C.c_int32),
+        ("bounds_given", C.c_int32), ("autotune", C.c_int32),
         ("tol", C.c_double), ("b_sup", C.c_double), ("mu_1", C.c_double), ("mu_ne", C.c_double),
         ("norm_est", C.c_double), ("mixed_switch", C.c_double), ("seed", C.c_uint64),
     ]

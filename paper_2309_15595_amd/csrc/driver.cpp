@@ -2,7 +2,7 @@
 // 1 x 1 grid (AllReduce = identity, B2 = C2), host scalar logic (bounds,
 // degree optimisation, CondEst, locking decisions) and the C ABI.
 //
-// Device work all runs in the hand-written kernels of zgemm.hip, cgemm.hip
+// Device work all runs in the hand-written kernels of zgemm.hip, zfilter.hip
 // and small.hip, except the n_e x n_e Hermitian eigensolve of Rayleigh-Ritz
 // (rocSOLVER zheevd) and the rarely taken Householder-QR fallback of Alg. 4
 // (rocSOLVER zgeqrf/zungqr).
@@ -17,8 +17,11 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -215,6 +218,7 @@ struct Workspace {
   c32* X32b = nullptr;
   void* tail_ws = nullptr;     // split-K tail of the big GEMMs
   int* tail_counters = nullptr;
+  z64* tune_scratch = nullptr; // autotuner output sink (N x ne), allocated on first use
   rocblas_handle rb = nullptr;
   std::vector<void*> owned;
 
@@ -288,6 +292,72 @@ struct Workspace {
 // Steps
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Tile-shape autotuner for the filter GEMM.  A size class is (order M, active
+// columns in steps of 32); the first time a class is seen the candidate
+// launches (tile configuration x tail policy) are timed on the real operands
+// with the output redirected to scratch, and the fastest is kept for the
+// life of the process.
+// ---------------------------------------------------------------------------
+struct FilterTuner {
+  std::mutex mu;
+  std::map<std::pair<int64_t, int64_t>, int> best;
+};
+static FilterTuner& filter_tuner() {
+  static FilterTuner t;
+  return t;
+}
+
+static int time_launches(const std::function<int()>& launch, hipStream_t s, float* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  CHASE_CHK(hipEventCreate(&a));
+  CHASE_CHK(hipEventCreate(&b));
+  int st = launch();  // warm-up
+  if (!st) {
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < 2 && !st; ++r) st = launch();
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    (void)hipEventElapsedTime(ms, a, b);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+
+static int tuned_choice(Workspace& w, const GemmArgs& g, hipStream_t s, int* choice) {
+  FilterTuner& T = filter_tuner();
+  const std::pair<int64_t, int64_t> key(g.M, (g.N + 31) / 32);
+  std::lock_guard<std::mutex> lock(T.mu);
+  auto it = T.best.find(key);
+  if (it != T.best.end()) {
+    *choice = it->second;
+    return kOk;
+  }
+  if (!w.tune_scratch) {
+    int st = w.alloc(&w.tune_scratch, (size_t)w.N * w.ne);
+    if (st) return st;
+    CHASE_CHK(hipMemsetAsync(w.tune_scratch, 0, sizeof(z64) * (size_t)w.N * w.ne, s));
+  }
+  GemmArgs t = g;
+  t.Y = w.tune_scratch;
+  t.ldy = g.M;
+  int bestc = kChoiceT0Tail;
+  float best_ms = 1e30f;
+  for (int c = 0; c < kNumChoices; ++c) {
+    float ms = 1e30f;
+    int st = time_launches([&]() { return zgemm_nn_big_launch(t, s, true, w.tail_ws, w.tail_counters, c); }, s, &ms);
+    if (st) return st;
+    if (ms < best_ms) {
+      best_ms = ms;
+      bestc = c;
+    }
+  }
+  T.best[key] = bestc;
+  *choice = bestc;
+  return kOk;
+}
+
 // Filter (Eq. 1 with the scaled Chebyshev coefficients): the GEMM of every
 // degree step.  V: N x n (the final iterate of an even degree lands back in
 // V), W: its ping-pong partner; degs ascending.  Step k computes X_{k+1} for
@@ -352,7 +422,7 @@ static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, in
 // scalars as run_filter, complex64 data, FP32 accumulation on MFMA).
 static int run_filter_fp32(const c32* A32, int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int64_t n,
                            const int32_t* degs, double c, double e, double mu1, int64_t* matvecs,
-                           int64_t* launches, hipStream_t s) {
+                           int64_t* launches, hipStream_t s, void* tail_ws, int* tail_counters) {
   if (n <= 0) return kOk;
   int st = convert_z_to_c(V, ldv, X0, N, N, n, s);
   if (st) return st;
@@ -392,7 +462,7 @@ static int run_filter_fp32(const c32* A32, int64_t N, z64* V, int64_t ldv, c32* 
     g.Y = out + s0 * N; g.ldy = N;
     g.Z = cur + s0 * N; g.ldz = N;
     g.alpha = (float)alpha; g.beta = (float)beta; g.gamma = (float)(-alpha * c);
-    st = cgemm_filter_launch(g, s);
+    st = cfilter_big_launch(g, s, tail_ws, tail_counters);
     if (st) return st;
     mv += cols;
     ++nl;
@@ -784,14 +854,17 @@ struct ProblemState {
     if (nlow > 0) {
       int64_t mv32 = 0, nl32 = 0;
       if ((st = run_filter_fp32(w->A32, N, V + (int64_t)locked * ldv, ldv, w->X32a, w->X32b, nlow,
-                                degs.data() + locked, c, e, mu1_cur, &mv32, &nl32, s)))
+                                degs.data() + locked, c, e, mu1_cur, &mv32, &nl32, s, w->tail_ws,
+                                w->tail_counters)))
         return st;
       S.filter_matvecs_fp32 += mv32;
       mv += mv32;
       nl += nl32;
     }
     for (const GemmArgs& g : plan()) {
-      if ((st = zgemm_nn_big_launch(g, s, true, w->tail_ws, w->tail_counters))) return st;
+      int choice = kChoiceT0Tail;
+      if (P.autotune && (st = tuned_choice(*w, g, s, &choice))) return st;
+      if ((st = zgemm_nn_big_launch(g, s, true, w->tail_ws, w->tail_counters, choice))) return st;
       mv += g.N;
       ++nl;
     }
@@ -1064,18 +1137,80 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
     const size_t tbytes = sizeof(GroupEntry) * (size_t)max_deg * count;
     CHASE_CHK(hipHostMalloc(reinterpret_cast<void**>(&h_table), tbytes, hipHostMallocDefault));
     CHASE_CHK(hipMalloc(reinterpret_cast<void**>(&d_table), tbytes));
-    int cus = 256;
     CHASE_CHK(hipGetDevice(&dev));
     for (int wk = 0; wk < nw; ++wk) CHASE_CHK(hipStreamCreate(&wstreams[wk]));
     CHASE_CHK(hipEventCreateWithFlags(&filtered, hipEventDisableTiming));
-    CHASE_CHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int grid = (int)(8 * cdiv(cus, 8));
+
+    t_all.start(s);
+    for (int i = 0; i < count; ++i) {
+      const void* st_i = starts ? starts[i] : nullptr;
+      if ((st = ps[i].setup(use_v0 ? use_v0[i] : 1, reinterpret_cast<const z64*>(st_i),
+                            st_i && ld_starts ? ld_starts[i] : 0, st_i && nstarts ? nstarts[i] : 0, s)))
+        return st;
+    }
+    // Fill the table with this iteration's filter GEMMs (plans) for tile
+    // configuration cfg, with the running tile count of every step.
+    std::vector<std::vector<GemmArgs>> plans(count);
+    auto build_table = [&](int cfg) -> int {
+      std::memset(h_table, 0, tbytes);
+      for (int i = 0; i < count; ++i) {
+        if (plans[i].size() > (size_t)max_deg) return -11;
+        for (size_t k = 0; k < plans[i].size(); ++k) {
+          GroupEntry& e = h_table[k * count + i];
+          e.g = plans[i][k];
+          zfilter_tiles(e.g.M, e.g.N, &e.tiles_n, cfg);
+        }
+      }
+      for (int k = 0; k < max_deg; ++k) {
+        int64_t acc = 0;
+        for (int i = 0; i < count; ++i) {
+          GroupEntry& e = h_table[(size_t)k * count + i];
+          acc += zfilter_tiles(e.g.M, e.g.N, nullptr, cfg);
+          e.tile_end = acc;
+        }
+      }
+      return kOk;
+    };
+    auto make_plans = [&]() -> int {
+      for (int i = 0; i < count; ++i) {
+        plans[i].clear();
+        if (!ps[i].active()) continue;
+        int r = ps[i].prepare(s);
+        if (r) return r;
+        plans[i] = ps[i].plan();
+      }
+      return kOk;
+    };
+    if ((st = make_plans())) return st;
+
+    // Tile shape: with autotuning, time degree step 0 of the real batch in
+    // both configurations (step 0 only writes the ping-pong buffers, so the
+    // trial launches change nothing) and keep the faster one.
+    int cfg = 0;
+    bool tune = false;
+    for (int i = 0; i < count; ++i) tune = tune || params[i].autotune;
+    if (tune) {
+      float best_ms = 1e30f;
+      for (int c = 0; c < 2; ++c) {
+        if ((st = build_table(c))) return st;
+        CHASE_CHK(hipMemcpyAsync(d_table, h_table, tbytes, hipMemcpyHostToDevice, s));
+        float ms = 1e30f;
+        if ((st = time_launches([&]() { return zfilter_grouped_launch(d_table, count, 0, grouped_grid(c), s, c); },
+                                s, &ms)))
+          return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          cfg = c;
+        }
+      }
+    }
     // One captured graph holds every degree step of the grouped filter; its
     // kernels read all parameters from d_table, so it is replayed unchanged.
+    const int grid = grouped_grid(cfg);
     CHASE_CHK(hipStreamCreate(&cs));
     CHASE_CHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < max_deg; ++k) {
-      if ((st = zfilter_grouped_launch(d_table, count, k, grid, cs))) {
+      if ((st = zfilter_grouped_launch(d_table, count, k, grid, cs, cfg))) {
         hipGraph_t g2 = nullptr;
         (void)hipStreamEndCapture(cs, &g2);
         if (g2) (void)hipGraphDestroy(g2);
@@ -1085,41 +1220,20 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
     CHASE_CHK(hipStreamEndCapture(cs, &graph));
     CHASE_CHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
 
-    t_all.start(s);
-    for (int i = 0; i < count; ++i) {
-      const void* st_i = starts ? starts[i] : nullptr;
-      if ((st = ps[i].setup(use_v0 ? use_v0[i] : 1, reinterpret_cast<const z64*>(st_i),
-                            st_i && ld_starts ? ld_starts[i] : 0, st_i && nstarts ? nstarts[i] : 0, s)))
-        return st;
-    }
+    bool first = true;
     while (true) {
       bool any = false;
       for (int i = 0; i < count; ++i) any = any || ps[i].active();
       if (!any) break;
-      std::memset(h_table, 0, tbytes);
+      if (!first && (st = make_plans())) return st;
+      first = false;
+      if ((st = build_table(cfg))) return st;
       for (int i = 0; i < count; ++i) {
-        if (!ps[i].active()) continue;
-        if ((st = ps[i].prepare(s))) return st;
-        const std::vector<GemmArgs> steps = ps[i].plan();
-        if ((int)steps.size() > max_deg) return -11;
         int64_t mv = 0;
-        for (size_t k = 0; k < steps.size(); ++k) {
-          GroupEntry& e = h_table[k * count + i];
-          e.g = steps[k];
-          zfilter_tiles(steps[k].M, steps[k].N, &e.tiles_n);
-          mv += steps[k].N;
-        }
+        for (const GemmArgs& g : plans[i]) mv += g.N;
         ps[i].S.filter_matvecs += mv;
-        ps[i].S.filter_launches += (int64_t)steps.size();
+        ps[i].S.filter_launches += (int64_t)plans[i].size();
         ps[i].total_mv += mv;
-      }
-      for (int k = 0; k < max_deg; ++k) {  // running tile counts per step
-        int64_t acc = 0;
-        for (int i = 0; i < count; ++i) {
-          GroupEntry& e = h_table[(size_t)k * count + i];
-          acc += zfilter_tiles(e.g.M, e.g.N, nullptr);
-          e.tile_end = acc;
-        }
       }
       CHASE_CHK(hipMemcpyAsync(d_table, h_table, tbytes, hipMemcpyHostToDevice, s));
       t_f.start(s);

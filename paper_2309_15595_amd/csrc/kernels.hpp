@@ -34,8 +34,14 @@ int tail_counters_init(int* counters, hipStream_t s);
 // Large NN products (filter step, H C): 128 x 128 tiles, double-buffered LDS
 // (zfilter.hip).  filter_symbol selects the kernel name reported by profilers.
 // With a tail workspace the last partial round of tiles is split along K.
+// choice (filter only): tile configuration and tail policy picked by the
+// autotuner.
+constexpr int kChoiceT0Tail = 0;    // 128 x 128, split-K tail
+constexpr int kChoiceT0NoTail = 1;  // 128 x 128, no tail split
+constexpr int kChoiceT1Tail = 2;    // 128 x 64, split-K tail
+constexpr int kNumChoices = 3;
 int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws = nullptr,
-                        int* tail_counters = nullptr);
+                        int* tail_counters = nullptr, int choice = kChoiceT0Tail);
 // One problem's filter GEMM in a grouped launch: tiles [tile_end - tiles,
 // tile_end) of the step's running tile count belong to it.
 struct GroupEntry {
@@ -43,11 +49,14 @@ struct GroupEntry {
   int64_t tiles_n = 1;
   int64_t tile_end = 0;
 };
-// Tiles of the filter kernel for an M x N output (tiles_n: column tiles).
-int64_t zfilter_tiles(int64_t M, int64_t N, int64_t* tiles_n);
+// Tiles of filter configuration cfg (0: 128 x 128, 1: 128 x 64) for an
+// M x N output (tiles_n: column tiles).
+int64_t zfilter_tiles(int64_t M, int64_t N, int64_t* tiles_n, int cfg = 0);
 // Persistent grouped filter step over row `step` of a device table of
-// `count` entries per step; grid a multiple of 8.
-int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s);
+// `count` entries per step; grid a multiple of 8 (see grouped_grid).
+int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s, int cfg = 0);
+// Grid filling every CU with resident workgroups of configuration cfg.
+int grouped_grid(int cfg);
 // Split over K into `splits` partial products in `ws`, summed in fixed order;
 // hermitise = 1 stores (S + S^H)/2 (M == N).
 int zgemm_splitk(int opa, int opb, const GemmArgs& g, void* ws, int splits, int hermitise,
@@ -64,7 +73,9 @@ struct CGemmArgs {
   const c32* Z = nullptr; int64_t ldz = 0;
   float alpha = 1.0f, beta = 0.0f, gamma = 0.0f;
 };
-int cgemm_filter_launch(const CGemmArgs& g, hipStream_t s);
+// FP32 filter step (zfilter.hip): same schedule, split-K tail and epilogue as
+// the FP64 one, on complex64 data with FP32 accumulation.
+int cfilter_big_launch(const CGemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters);
 
 // ---- small dense kernels (small.hip) --------------------------------------
 // Blocked lower Cholesky G = L L^H in place (lower part), n x n, ld.

@@ -22,9 +22,6 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
-#ifndef ZF_CONFIG
-#define ZF_CONFIG 4
-#endif
 
 namespace chase {
 
@@ -32,6 +29,32 @@ namespace {
 
 struct alignas(16) zv {
   double re, im;
+};
+
+// Precision of one filter instantiation: element and accumulator types, the
+// MFMA, and the row of accumulator element r in lane group kq (16x16x4 f64:
+// kq + 4 r; 16x16x4 f32: 4 kq + r, both measured on gfx950).
+struct PF64 {
+  using real = double;
+  struct alignas(16) cplx {
+    double re, im;
+  };
+  using acc = f64x4;
+  static __device__ __forceinline__ acc mma(real a, real b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
+};
+struct PF32 {
+  using real = float;
+  struct alignas(8) cplx {
+    float re, im;
+  };
+  using acc = f32x4;
+  static __device__ __forceinline__ acc mma(real a, real b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
 };
 
 __device__ __forceinline__ bool map_tile(int64_t ntiles, int64_t tiles_n, int64_t& tm, int64_t& tn) {
@@ -84,10 +107,10 @@ struct Cfg {
   static_assert(NT % BM == 0 || BM % NT == 0, "A load mapping");
 };
 
-template <class C, int BK>
+template <class P, class C, int BK>
 struct Smem {
-  double a[2][2][BK][C::APAD];  // [buffer][re/im][k][m]
-  double b[2][2][BK][C::BPAD];  // [buffer][re/im][k][n]
+  typename P::real a[2][2][BK][C::APAD];  // [buffer][re/im][k][m]
+  typename P::real b[2][2][BK][C::BPAD];  // [buffer][re/im][k][n]
 };
 
 // One BM x BN output tile (tm, tn) of g.  EDGE tiles overhang the output:
@@ -97,11 +120,14 @@ struct Smem {
 // kbeg/kend (multiples of BK) restrict the K range; with part != nullptr the
 // raw accumulator tile is stored there (tile-local, m fastest) instead of
 // applying the epilogue.
-template <int WGM, int WGN, int TM, int TN, int BK, bool EDGE>
+template <class P, int WGM, int WGN, int TM, int TN, int BK, bool EDGE>
 __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg,
-                                               int64_t kend, zv* part,
-                                               Smem<Cfg<WGM, WGN, TM, TN, BK>, BK>& s) {
+                                               int64_t kend, typename P::cplx* part,
+                                               Smem<P, Cfg<WGM, WGN, TM, TN, BK>, BK>& s) {
   using C = Cfg<WGM, WGN, TM, TN, BK>;
+  using zv = typename P::cplx;
+  using real = typename P::real;
+  using accv = typename P::acc;
   constexpr int NT = C::NT, BM = C::BM, BN = C::BN, LA = C::LA, LB = C::LB;
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int t = threadIdx.x;
@@ -116,13 +142,13 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
     vnb = (int)(rn <= 0 ? 0 : (rn >= TN * 16 ? TN : (rn + 15) / 16));
   }
 
-  f64x4 cr[TN][TM], ci[TN][TM];
+  accv cr[TN][TM], ci[TN][TM];
 #pragma unroll
   for (int a = 0; a < TN; ++a)
 #pragma unroll
     for (int b = 0; b < TM; ++b) {
-      cr[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-      ci[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+      cr[a][b] = accv{0, 0, 0, 0};
+      ci[a][b] = accv{0, 0, 0, 0};
     }
 
   const zv* A = reinterpret_cast<const zv*>(g.A);
@@ -133,13 +159,13 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
     for (int r = 0; r < LA; ++r) {
       const int e = t + NT * r;
       const int64_t m = m0 + (e % BM), k = k0 + (e / BM);
-      ra[r] = (m < g.M && k < kend) ? A[m + k * g.lda] : zv{0.0, 0.0};
+      ra[r] = (m < g.M && k < kend) ? A[m + k * g.lda] : zv{0, 0};
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       const int e = t + NT * r;
       const int64_t k = k0 + (e % BK), n = n0 + (e / BK);
-      rb[r] = (n < g.N && k < kend) ? B[k + n * g.ldb] : zv{0.0, 0.0};
+      rb[r] = (n < g.N && k < kend) ? B[k + n * g.ldb] : zv{0, 0};
     }
   };
   auto sstore = [&](int buf) {
@@ -188,7 +214,7 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kk = ks * 4 + kq;
-      double br[TN], bi[TN], ar[TM], ai[TM];
+      real br[TN], bi[TN], ar[TM], ai[TM];
 #pragma unroll
       for (int i = 0; i < TN; ++i) {
         br[i] = s.b[buf][0][kk][wn * TN * 16 + i * 16 + l16];
@@ -204,16 +230,16 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
 #pragma unroll
         for (int mb = 0; mb < TM; ++mb) {
           if (EDGE && (nb >= vnb || mb >= vmb)) continue;
-          cr[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[nb], ar[mb], cr[nb][mb], 0, 0, 0);
-          ci[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[nb], ai[mb], ci[nb][mb], 0, 0, 0);
+          cr[nb][mb] = P::mma(br[nb], ar[mb], cr[nb][mb]);
+          ci[nb][mb] = P::mma(br[nb], ai[mb], ci[nb][mb]);
         }
 #pragma unroll
       for (int nb = 0; nb < TN; ++nb)
 #pragma unroll
         for (int mb = 0; mb < TM; ++mb) {
           if (EDGE && (nb >= vnb || mb >= vmb)) continue;
-          cr[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi[nb], ai[mb], cr[nb][mb], 0, 0, 0);
-          ci[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[nb], ar[mb], ci[nb][mb], 0, 0, 0);
+          cr[nb][mb] = P::mma(-bi[nb], ai[mb], cr[nb][mb]);
+          ci[nb][mb] = P::mma(bi[nb], ar[mb], ci[nb][mb]);
         }
     }
 #if ZF_PREFETCH2
@@ -239,7 +265,7 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
       for (int mb = 0; mb < TM; ++mb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int nl = wn * TN * 16 + nb * 16 + kq + 4 * r;
+          const int nl = wn * TN * 16 + nb * 16 + P::row(kq, r);
           const int ml = wm * TM * 16 + mb * 16 + l16;
           part[ml + nl * BM] = zv{cr[nb][mb][r], ci[nb][mb][r]};
         }
@@ -253,34 +279,35 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
     for (int mb = 0; mb < TM; ++mb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t n = n0 + wn * TN * 16 + nb * 16 + kq + 4 * r;
+        const int64_t n = n0 + wn * TN * 16 + nb * 16 + P::row(kq, r);
         const int64_t m = m0 + wm * TM * 16 + mb * 16 + l16;
         if (m >= g.M || n >= g.N) continue;
-        zv out{g.alpha * cr[nb][mb][r], g.alpha * ci[nb][mb][r]};
+        const real al = (real)g.alpha, be = (real)g.beta, ga = (real)g.gamma;
+        zv out{al * cr[nb][mb][r], al * ci[nb][mb][r]};
         if (g.beta != 0.0) {
           const zv y = Y[m + n * g.ldy];
-          out.re += g.beta * y.re;
-          out.im += g.beta * y.im;
+          out.re += be * y.re;
+          out.im += be * y.im;
         }
         if (g.gamma != 0.0) {
           const zv z = Z[m + n * g.ldz];
-          out.re += g.gamma * z.re;
-          out.im += g.gamma * z.im;
+          out.re += ga * z.re;
+          out.im += ga * z.im;
         }
         Y[m + n * g.ldy] = out;
       }
 }
 
-template <int WGM, int WGN, int TM, int TN, int BK>
+template <class P, int WGM, int WGN, int TM, int TN, int BK>
 __device__ __forceinline__ void zbig_tile(const GemmArgs& g, int64_t tm, int64_t tn,
-                                          Smem<Cfg<WGM, WGN, TM, TN, BK>, BK>& s, int64_t kbeg = 0,
-                                          int64_t kend = -1, zv* part = nullptr) {
+                                          Smem<P, Cfg<WGM, WGN, TM, TN, BK>, BK>& s, int64_t kbeg = 0,
+                                          int64_t kend = -1, typename P::cplx* part = nullptr) {
   using C = Cfg<WGM, WGN, TM, TN, BK>;
   if (kend < 0) kend = g.K;
   if ((tm + 1) * C::BM <= g.M && (tn + 1) * C::BN <= g.N)
-    zbig_tile_impl<WGM, WGN, TM, TN, BK, false>(g, tm, tn, kbeg, kend, part, s);
+    zbig_tile_impl<P, WGM, WGN, TM, TN, BK, false>(g, tm, tn, kbeg, kend, part, s);
   else
-    zbig_tile_impl<WGM, WGN, TM, TN, BK, true>(g, tm, tn, kbeg, kend, part, s);
+    zbig_tile_impl<P, WGM, WGN, TM, TN, BK, true>(g, tm, tn, kbeg, kend, part, s);
 }
 
 // Whole launch: tiles [0, tail.full) one per workgroup (XCD-major), then
@@ -289,11 +316,13 @@ __device__ __forceinline__ void zbig_tile(const GemmArgs& g, int64_t tm, int64_t
 // counts itself in; the last segment of a tile to arrive sums the partials
 // in segment order (deterministic), applies the epilogue and resets the
 // counter for the next launch.  No workgroup ever waits on another.
-template <int WGM, int WGN, int TM, int TN, int BK>
+template <class P, int WGM, int WGN, int TM, int TN, int BK>
 __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& tail) {
   using C = Cfg<WGM, WGN, TM, TN, BK>;
+  using zv = typename P::cplx;
+  using real = typename P::real;
   constexpr int BM = C::BM, BN = C::BN;
-  __shared__ Smem<C, BK> s;
+  __shared__ Smem<P, C, BK> s;
   __shared__ int last;
   const int64_t tiles_n = (g.N + BN - 1) / BN;
   const int64_t grid_main = 8 * ((tail.full + 7) / 8);
@@ -308,7 +337,7 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& ta
 #else
     if (!map_tile(tail.full, tiles_n, tm, tn)) return;
 #endif
-    zbig_tile<WGM, WGN, TM, TN, BK>(g, tm, tn, s);
+    zbig_tile<P, WGM, WGN, TM, TN, BK>(g, tm, tn, s);
     return;
   }
   const int64_t j = (int64_t)blockIdx.x - grid_main;       // tail segment
@@ -320,7 +349,7 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& ta
   const int64_t kbeg = sp * per * BK;
   const int64_t kend = (sp + 1) * per * BK < g.K ? (sp + 1) * per * BK : g.K;
   zv* part = reinterpret_cast<zv*>(tail.ws) + j * (int64_t)(BM * BN);
-  zbig_tile<WGM, WGN, TM, TN, BK>(g, tm, tn, s, kbeg, kend, part);
+  zbig_tile<P, WGM, WGN, TM, TN, BK>(g, tm, tn, s, kbeg, kend, part);
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) last = (atomicAdd(tail.counters + tl, 1) == tail.ksplit - 1);
@@ -334,22 +363,23 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& ta
   for (int e = threadIdx.x; e < BM * BN; e += C::NT) {
     const int64_t m = m0 + e % BM, n = n0 + e / BM;
     if (m >= g.M || n >= g.N) continue;
-    double sr = 0.0, si = 0.0;
+    real sr = 0, si = 0;
     for (int q = 0; q < tail.ksplit; ++q) {
       const zv v = parts[q * (int64_t)(BM * BN) + e];
       sr += v.re;
       si += v.im;
     }
-    zv out{g.alpha * sr, g.alpha * si};
+    const real al = (real)g.alpha, be = (real)g.beta, ga = (real)g.gamma;
+    zv out{al * sr, al * si};
     if (g.beta != 0.0) {
       const zv y = Y[m + n * g.ldy];
-      out.re += g.beta * y.re;
-      out.im += g.beta * y.im;
+      out.re += be * y.re;
+      out.im += be * y.im;
     }
     if (g.gamma != 0.0) {
       const zv z = Z[m + n * g.ldz];
-      out.re += g.gamma * z.re;
-      out.im += g.gamma * z.im;
+      out.re += ga * z.re;
+      out.im += ga * z.im;
     }
     Y[m + n * g.ldy] = out;
   }
@@ -364,7 +394,7 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& ta
 template <int WGM, int WGN, int TM, int TN, int BK>
 __device__ __forceinline__ void zbig_grouped(const GroupEntry* __restrict__ table, int count, int step) {
   using C = Cfg<WGM, WGN, TM, TN, BK>;
-  __shared__ Smem<C, BK> s;
+  __shared__ Smem<PF64, C, BK> s;
   const GroupEntry* __restrict__ row = table + (int64_t)step * count;
   const int64_t total = row[count - 1].tile_end;
   if (total <= 0) return;
@@ -380,48 +410,51 @@ __device__ __forceinline__ void zbig_grouped(const GroupEntry* __restrict__ tabl
     const int64_t lt = t - begin;
     const GemmArgs g = row[p].g;
     const int64_t tiles_n = row[p].tiles_n;
-    zbig_tile<WGM, WGN, TM, TN, BK>(g, lt / tiles_n, lt % tiles_n, s);
+    zbig_tile<PF64, WGM, WGN, TM, TN, BK>(g, lt / tiles_n, lt % tiles_n, s);
   }
 }
 
-// Configuration: (waves along m, waves along n, 16-blocks per wave m, n, K tile)
-#if ZF_CONFIG == 1
-#define ZF_ARGS 2, 4, 4, 2, 16   // 128 x 128 tile, 8 waves of 64 x 32
-#elif ZF_CONFIG == 2
-#define ZF_ARGS 2, 2, 4, 2, 16   // 128 x 64 tile, 4 waves of 64 x 32
-#elif ZF_CONFIG == 3
-#define ZF_ARGS 4, 2, 2, 4, 16   // 128 x 128 tile, 8 waves of 32 x 64
-#elif ZF_CONFIG == 4
-#define ZF_ARGS 2, 4, 4, 2, 8    // 128 x 128 tile, 8 waves, K tile 8
-#endif
+// Tile configurations (waves along m, waves along n, 16-blocks per wave
+// along m and n, K tile):
+//   T0: 128 x 128 complex tile, 8 waves of 64 x 32, one workgroup per CU;
+//   T1: 128 x 64, 4 waves of 64 x 32, two workgroups per CU (finer tiles
+//       for few active columns).
+// Which one a launch uses is decided by the autotuner in the driver.
+#define T0_ARGS 2, 4, 4, 2, 8
+#define T1_ARGS 2, 2, 4, 2, 8
+using C0 = Cfg<T0_ARGS>;
+using C1 = Cfg<T1_ARGS>;
 
-using ZC = Cfg<ZF_ARGS>;
-
-__global__ __launch_bounds__(ZC::NT, 1) void zfilter_step(GemmArgs g, TailSplit t) { zbig_body<ZF_ARGS>(g, t); }
+__global__ __launch_bounds__(C0::NT, 1) void zfilter_step(GemmArgs g, TailSplit t) { zbig_body<PF64, T0_ARGS>(g, t); }
+__global__ __launch_bounds__(C1::NT, 2) void zfilter_step_n64(GemmArgs g, TailSplit t) {
+  zbig_body<PF64, T1_ARGS>(g, t);
+}
 // Same schedule for the other large H-times-block products (Rayleigh-Ritz H C).
-__global__ __launch_bounds__(ZC::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit t) { zbig_body<ZF_ARGS>(g, t); }
+__global__ __launch_bounds__(C0::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit t) { zbig_body<PF64, T0_ARGS>(g, t); }
+// FP32 filter step of the mixed-precision solve (complex64 H and X, FP32
+// accumulation): 128 x 128 tile, 8 waves of 64 x 32, K tile 16.
+#define TF32_ARGS 2, 4, 4, 2, 16
+using CF = Cfg<TF32_ARGS>;
+__global__ __launch_bounds__(CF::NT, 1) void cfilter_step(GemmArgs g, TailSplit t) { zbig_body<PF32, TF32_ARGS>(g, t); }
+__global__ __launch_bounds__(C0::NT, 1) void zfilter_grouped(const GroupEntry* __restrict__ table, int count,
+                                                             int step) {
+  zbig_grouped<T0_ARGS>(table, count, step);
+}
+__global__ __launch_bounds__(C1::NT, 2) void zfilter_grouped_n64(const GroupEntry* __restrict__ table, int count,
+                                                                 int step) {
+  zbig_grouped<T1_ARGS>(table, count, step);
+}
 __global__ void counters_zero(int* c, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) c[i] = 0;
 }
-__global__ __launch_bounds__(ZC::NT, 1) void zfilter_grouped(const GroupEntry* __restrict__ table, int count, int step) {
-  zbig_grouped<ZF_ARGS>(table, count, step);
-}
+
+struct CfgInfo {
+  int bm, bn, bk, nt, wg_per_cu;
+};
+constexpr CfgInfo kCfg[2] = {{C0::BM, C0::BN, C0::BK_, C0::NT, 1}, {C1::BM, C1::BN, C1::BK_, C1::NT, 2}};
 
 }  // namespace
-
-int64_t zfilter_tiles(int64_t M, int64_t N, int64_t* tiles_n) {
-  if (tiles_n) *tiles_n = cdiv(N, ZC::BN);
-  if (M <= 0 || N <= 0) return 0;
-  return cdiv(M, ZC::BM) * cdiv(N, ZC::BN);
-}
-
-int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s) {
-  if (count <= 0 || grid <= 0 || grid % 8) return -1;
-  hipLaunchKernelGGL(zfilter_grouped, dim3((unsigned)grid), dim3(ZC::NT), 0, s, table, count, step);
-  CHASE_CHK_LAUNCH();
-  return kOk;
-}
 
 static int cu_count() {
   static int cus = 0;
@@ -434,7 +467,26 @@ static int cu_count() {
   return cus;
 }
 
-int64_t tail_workspace_bytes() { return (int64_t)kTailMaxSegments * ZC::BM * ZC::BN * 16; }
+int64_t zfilter_tiles(int64_t M, int64_t N, int64_t* tiles_n, int cfg) {
+  const CfgInfo& c = kCfg[cfg & 1];
+  if (tiles_n) *tiles_n = cdiv(N, c.bn);
+  if (M <= 0 || N <= 0) return 0;
+  return cdiv(M, c.bm) * cdiv(N, c.bn);
+}
+
+int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s, int cfg) {
+  if (count <= 0 || grid <= 0 || grid % 8) return -1;
+  if (cfg == 1)
+    hipLaunchKernelGGL(zfilter_grouped_n64, dim3((unsigned)grid), dim3(C1::NT), 0, s, table, count, step);
+  else
+    hipLaunchKernelGGL(zfilter_grouped, dim3((unsigned)grid), dim3(C0::NT), 0, s, table, count, step);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int grouped_grid(int cfg) { return (int)(8 * cdiv((int64_t)cu_count() * kCfg[cfg & 1].wg_per_cu, 8)); }
+
+int64_t tail_workspace_bytes() { return (int64_t)kTailMaxSegments * C0::BM * C0::BN * 16; }
 
 int tail_counters_init(int* counters, hipStream_t s) {
   hipLaunchKernelGGL(counters_zero, dim3((kTailMaxSegments + 255) / 256), dim3(256), 0, s, counters,
@@ -443,22 +495,26 @@ int tail_counters_init(int* counters, hipStream_t s) {
   return kOk;
 }
 
-int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws, int* tail_counters) {
+int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws, int* tail_counters,
+                        int choice) {
   if (g.M <= 0 || g.N <= 0) return kOk;
   if (g.ws != nullptr || g.upper_b || g.lower_only || g.bscale != nullptr) return -1;
-  const int64_t tiles = cdiv(g.M, ZC::BM) * cdiv(g.N, ZC::BN);
-  const int64_t G = cu_count();  // one workgroup per CU (LDS and registers)
+  const int cfg = (choice == kChoiceT1Tail && filter_symbol) ? 1 : 0;
+  const CfgInfo& c = kCfg[cfg];
+  const int64_t tiles = cdiv(g.M, c.bm) * cdiv(g.N, c.bn);
+  const int64_t G = (int64_t)cu_count() * c.wg_per_cu;  // concurrently resident workgroups
   TailSplit t;
   t.full = tiles;
   t.ksplit = 1;
   t.ws = tail_ws;
   t.counters = tail_counters;
-  const int64_t nkt = cdiv(g.K, ZC::BK_);
+  const int64_t nkt = cdiv(g.K, c.bk);
   const int64_t rem = tiles % G;
+  bool use_tail = tail_ws && tail_counters && rem > 0 && choice != kChoiceT0NoTail;
 #ifdef ZF_NO_TAIL
-  tail_ws = nullptr;
+  use_tail = false;
 #endif
-  if (tail_ws && tail_counters && rem > 0) {
+  if (use_tail) {
     // split the last round's tiles along K to fill the idle CUs: minimise
     // ceil(rem * s / G) / s (in units of one tile's time)
     int best = 1;
@@ -479,16 +535,59 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
   int64_t grid = 8 * cdiv(t.full, 8) + (tiles - t.full) * t.ksplit;
 #if ZF_GROUP_M > 0
   if (t.ksplit == 1) {  // grouped order: 8 x (most panels on one XCD x column tiles)
-    const int64_t tm_all = cdiv(g.M, ZC::BM);
-    grid = 8 * (cdiv(tm_all, 8) * cdiv(g.N, ZC::BN));
+    grid = 8 * (cdiv(cdiv(g.M, c.bm), 8) * cdiv(g.N, c.bn));
   }
 #endif
   GemmArgs a = g;
   if (a.K <= 0) a.alpha = 0.0;
-  if (filter_symbol)
-    hipLaunchKernelGGL(zfilter_step, dim3((unsigned)grid), dim3(ZC::NT), 0, s, a, t);
+  if (!filter_symbol)
+    hipLaunchKernelGGL(zgemm_nn_big, dim3((unsigned)grid), dim3(C0::NT), 0, s, a, t);
+  else if (cfg == 1)
+    hipLaunchKernelGGL(zfilter_step_n64, dim3((unsigned)grid), dim3(C1::NT), 0, s, a, t);
   else
-    hipLaunchKernelGGL(zgemm_nn_big, dim3((unsigned)grid), dim3(ZC::NT), 0, s, a, t);
+    hipLaunchKernelGGL(zfilter_step, dim3((unsigned)grid), dim3(C0::NT), 0, s, a, t);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int cfilter_big_launch(const CGemmArgs& c, hipStream_t s, void* tail_ws, int* tail_counters) {
+  if (c.M <= 0 || c.N <= 0) return kOk;
+  // The kernel reads operands through the same argument block as the FP64
+  // one; pointers are reinterpreted as complex64 inside.
+  GemmArgs g;
+  g.M = c.M; g.N = c.N; g.K = c.K;
+  g.A = reinterpret_cast<const z64*>(c.A); g.lda = c.lda;
+  g.B = reinterpret_cast<const z64*>(c.B); g.ldb = c.ldb;
+  g.Y = reinterpret_cast<z64*>(c.Y); g.ldy = c.ldy;
+  g.Z = reinterpret_cast<const z64*>(c.Z); g.ldz = c.ldz;
+  g.alpha = c.alpha; g.beta = c.beta; g.gamma = c.gamma;
+  if (g.K <= 0) g.alpha = 0.0;
+  const int64_t tiles = cdiv(g.M, CF::BM) * cdiv(g.N, CF::BN);
+  const int64_t G = cu_count();
+  TailSplit t;
+  t.full = tiles;
+  t.ws = tail_ws;
+  t.counters = tail_counters;
+  const int64_t nkt = cdiv(g.K, CF::BK_);
+  const int64_t rem = tiles % G;
+  if (tail_ws && tail_counters && rem > 0) {
+    int best = 1;
+    double cost_best = 1.0;
+    for (int sp = 2; sp <= 8; ++sp) {
+      if (nkt < 16 * sp || rem * sp > kTailMaxSegments) break;
+      const double cost = (double)cdiv(rem * sp, G) / sp;
+      if (cost < cost_best - 1e-9) {
+        cost_best = cost;
+        best = sp;
+      }
+    }
+    if (best > 1) {
+      t.full = tiles - rem;
+      t.ksplit = best;
+    }
+  }
+  const int64_t grid = 8 * cdiv(t.full, 8) + (tiles - t.full) * t.ksplit;
+  hipLaunchKernelGGL(cfilter_step, dim3((unsigned)grid), dim3(CF::NT), 0, s, g, t);
   CHASE_CHK_LAUNCH();
   return kOk;
 }

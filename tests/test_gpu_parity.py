@@ -307,3 +307,43 @@ def test_autograd_matches_dense_eigh(L):
     (ref * torch.from_numpy(w)).sum().backward()
     assert abs(loss.item() - float((ref * torch.from_numpy(w)).sum())) <= 1e-10 * p.norm2
     assert torch.max(torch.abs(A.grad.cpu() - Acpu.grad)).item() <= 1e-8
+
+
+def test_autograd_dense_gradient_2000(L):
+    """dL/dA of L = sum w_i lambda_i at N = 2000 (nev 80, nex 16) against the
+    gradient from a dense eigendecomposition on the CPU."""
+    from paper_2309_15595_amd.api import eigvalsh_lowest
+    p = synth.make_problem(2000, 80, 16, spectrum="dft", basis="gaussian", seed=2312)
+    w = synth.problems.loss_weights(80)
+    A = torch.from_numpy(p.A).cuda().requires_grad_(True)
+    V0 = torch.from_numpy(p.V0).cuda()
+    S = torch.from_numpy(p.starts).cuda()
+    lam = eigvalsh_lowest(A, 80, 16, V0=V0, starts=S)
+    (lam * torch.from_numpy(w).cuda()).sum().backward()
+    G = A.grad.cpu().numpy()
+    ev, X = np.linalg.eigh(p.A)
+    ref = (X[:, :80] * w) @ X[:, :80].conj().T
+    assert np.max(np.abs(lam.detach().cpu().numpy() - ev[:80])) <= 1e-10 * p.norm2
+    # eigenvector error ~ resid / gap: resid <= 1e-10 ||A||, gaps here >= ~1e-3
+    assert np.max(np.abs(G - ref)) <= 1e-6, np.max(np.abs(G - ref))
+
+
+def test_autograd_finite_difference_200(L):
+    """Central difference of L(A + hE) through the GPU solve vs <G, E>."""
+    from paper_2309_15595_amd.api import eigvalsh_lowest
+    p = synth.make_problem(200, 8, 4, spectrum="dft", basis="gaussian", seed=2313)
+    w = synth.problems.loss_weights(8)
+    rng = np.random.default_rng(5)
+    E = synth.complex_gaussian(rng, (200, 200))
+    E = 0.5 * (E + E.conj().T)
+    kw = dict(V0=torch.from_numpy(p.V0).cuda(), starts=torch.from_numpy(p.starts).cuda())
+    A = torch.from_numpy(p.A).cuda().requires_grad_(True)
+    lam = eigvalsh_lowest(A, 8, 4, **kw)
+    (lam * torch.from_numpy(w).cuda()).sum().backward()
+    an = float(np.real(np.vdot(A.grad.cpu().numpy(), E)))
+    h = 1e-5 * p.norm2
+    Lp = float(np.dot(w, eigvalsh_lowest(torch.from_numpy(p.A + h * E).cuda(), 8, 4, **kw).cpu().numpy()))
+    Lm = float(np.dot(w, eigvalsh_lowest(torch.from_numpy(p.A - h * E).cuda(), 8, 4, **kw).cpu().numpy()))
+    fd = (Lp - Lm) / (2 * h)
+    # solver error <= tol ||A|| per eigenvalue -> FD error ~ 1e-10 ||A|| / h
+    assert abs(fd - an) <= 1e-4 * max(1.0, abs(an)), (fd, an)
