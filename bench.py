@@ -188,26 +188,29 @@ def main():
     if not args.no_mixed:
         del solver
         torch.cuda.empty_cache()
-        with Solver(N, nev, nex, deg=20, max_deg=36, opt=1, tol=1e-10,
-                    precision=L.CHASE_FP32_MIXED, mixed_switch=1e-6) as ms:
-            mruns = []
-            for i in range(1 + 1):   # one warm-up, one timed
-                V.copy_(V0)
-                mruns.append(ms.solve_colmajor(A, V, True, S))
-            mritz, mresid, minfo = mruns[-1]
-        mst = minfo.stats
-        out["mixed"] = {
-            "precision": "fp32 filter + fp64 refinement",
-            "time_to_solution_s": mst["t_total"],
-            "speedup_vs_fp64": float(np.median(tts)) / mst["t_total"],
-            "filter_tflops_algorithmic": mst["filter_flops"] / mst["t_filter"] / 1e12,
-            "fp32_matvec_fraction": mst["filter_matvecs_fp32"] / max(1, mst["filter_matvecs"]),
-            "converged": bool(minfo.converged),
-            "max_abs_eig_err_vs_fp64_over_normA": float(np.max(np.abs(mritz - ritz)) / normA),
-            "max_abs_eig_err_vs_exact_over_normA": float(np.max(np.abs(mritz - lam[:nev])) / normA),
-            "max_resid_over_normA": float(np.max(mresid) / normA),
-            "iterations": mst["iterations"]}
-        log(args, f"mixed: {mst['t_total']:.2f} s")
+        out["mixed"] = {}
+        for name, code in (("fp32", L.CHASE_FP32_MIXED), ("bf16x3", L.CHASE_BF16X3_MIXED)):
+            with Solver(N, nev, nex, deg=20, max_deg=36, opt=1, tol=1e-10, precision=code,
+                        mixed_switch=1e-6, bf16_switch=1e-4) as ms:
+                mruns = []
+                for i in range(1 + 1):   # one warm-up, one timed
+                    V.copy_(V0)
+                    mruns.append(ms.solve_colmajor(A, V, True, S))
+                mritz, mresid, minfo = mruns[-1]
+            mst = minfo.stats
+            out["mixed"][name] = {
+                "ladder": "fp32 -> fp64" if name == "fp32" else "bf16x3 -> fp32 -> fp64",
+                "time_to_solution_s": mst["t_total"],
+                "speedup_vs_fp64": float(np.median(tts)) / mst["t_total"],
+                "filter_tflops_algorithmic": mst["filter_flops"] / mst["t_filter"] / 1e12,
+                "matvec_share": {"bf16x3": mst["filter_matvecs_bf16"] / max(1, mst["filter_matvecs"]),
+                                 "fp32": mst["filter_matvecs_fp32"] / max(1, mst["filter_matvecs"])},
+                "converged": bool(minfo.converged),
+                "max_abs_eig_err_vs_fp64_over_normA": float(np.max(np.abs(mritz - ritz)) / normA),
+                "max_abs_eig_err_vs_exact_over_normA": float(np.max(np.abs(mritz - lam[:nev])) / normA),
+                "max_resid_over_normA": float(np.max(mresid) / normA),
+                "iterations": mst["iterations"]}
+            log(args, f"mixed {name}: {mst['t_total']:.2f} s")
 
     if not args.no_cpu:
         A_host = A.cpu().numpy()

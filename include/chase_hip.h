@@ -39,9 +39,11 @@ extern "C" {
 typedef void* chase_stream_t; /* a hipStream_t; NULL = the default stream */
 
 enum {
-  CHASE_FP64 = 0,      /* every step in FP64 */
-  CHASE_FP32_MIXED = 1 /* filter GEMMs in FP32 until a vector's residual reaches
-                          the FP32 floor, then FP64; QR, RR, residuals in FP64 */
+  CHASE_FP64 = 0,       /* every step in FP64 */
+  CHASE_FP32_MIXED = 1, /* filter GEMMs in FP32 until a vector's residual reaches
+                           the FP32 floor, then FP64; QR, RR, residuals in FP64 */
+  CHASE_BF16X3_MIXED = 2 /* filter in BF16x3 split products (FP32 accumulate)
+                            down to the BF16x3 floor, then FP32, then FP64 */
 };
 
 enum {
@@ -71,6 +73,7 @@ typedef struct {
   double tol;           /* residual threshold relative to ||H|| (1e-10) */
   double b_sup, mu_1, mu_ne, norm_est;
   double mixed_switch;  /* FP32 -> FP64 switch at resd <= mixed_switch * ||H|| (1e-6) */
+  double bf16_switch;   /* BF16x3 -> FP32 switch at resd <= bf16_switch * ||H|| (1e-4) */
   uint64_t seed;        /* generator of the initial block / Lanczos starts when
                            the caller supplies none */
 } chase_params_t;
@@ -83,9 +86,10 @@ typedef struct {
   int32_t pad0;
   int64_t filter_matvecs;   /* sum over iterations of sum_j d_j */
   int64_t filter_matvecs_fp32; /* of which in FP32 (mixed precision) */
+  int64_t filter_matvecs_bf16; /* of which in BF16x3 (mixed precision) */
   int64_t total_matvecs;    /* filter + Lanczos + Rayleigh-Ritz + residual */
   int64_t filter_launches;  /* filter GEMM launches (one per degree step) */
-  double filter_flops;      /* 8 N^2 filter_matvecs */
+  double filter_flops;      /* 8 N^2 filter_matvecs (algorithmic, any precision) */
   double t_total, t_lanczos, t_filter, t_qr, t_rr, t_resid; /* seconds (HIP events) */
   double bounds[4];         /* b_sup, mu_1, mu_ne, norm_est actually used */
 } chase_stats_t;

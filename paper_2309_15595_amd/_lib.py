@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libchase_hip.so")
 
 CHASE_FP64 = 0
 CHASE_FP32_MIXED = 1
+CHASE_BF16X3_MIXED = 2
 CHASE_QR_AUTO = -1
 CHASE_QR_CHOLQR1 = 0
 CHASE_QR_CHOLQR2 = 1
@@ -27,7 +28,8 @@ class chase_params_t(C.Structure):
         ("precision", C.c_int32), ("lanczos_steps", C.c_int32), ("force_qr", C.c_int32),
         ("bounds_given", C.c_int32), ("autotune", C.c_int32),
         ("tol", C.c_double), ("b_sup", C.c_double), ("mu_1", C.c_double), ("mu_ne", C.c_double),
-        ("norm_est", C.c_double), ("mixed_switch", C.c_double), ("seed", C.c_uint64),
+        ("norm_est", C.c_double), ("mixed_switch", C.c_double), ("bf16_switch", C.c_double),
+        ("seed", C.c_uint64),
     ]
 
 
@@ -36,6 +38,7 @@ class chase_stats_t(C.Structure):
         ("status", C.c_int32), ("iterations", C.c_int32), ("locked", C.c_int32),
         ("qr_count", C.c_int32 * 4), ("pad0", C.c_int32),
         ("filter_matvecs", C.c_int64), ("filter_matvecs_fp32", C.c_int64),
+        ("filter_matvecs_bf16", C.c_int64),
         ("total_matvecs", C.c_int64), ("filter_launches", C.c_int64),
         ("filter_flops", C.c_double), ("t_total", C.c_double), ("t_lanczos", C.c_double),
         ("t_filter", C.c_double), ("t_qr", C.c_double), ("t_rr", C.c_double),

@@ -18,7 +18,7 @@ import torch
 from . import _lib
 
 _PRECISIONS = {"fp64": _lib.CHASE_FP64, "fp32": _lib.CHASE_FP32_MIXED,
-               "mixed": _lib.CHASE_FP32_MIXED}
+               "mixed": _lib.CHASE_FP32_MIXED, "bf16x3": _lib.CHASE_BF16X3_MIXED}
 
 
 def colmajor(x, device="cuda") -> torch.Tensor:

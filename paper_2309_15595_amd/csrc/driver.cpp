@@ -216,6 +216,8 @@ struct Workspace {
   c32* A32 = nullptr;
   c32* X32a = nullptr;
   c32* X32b = nullptr;
+  uint16_t* P16 = nullptr;     // BF16x3 planes of conj(H) (4 x ldp x N)
+  int64_t ldp = 0;
   void* tail_ws = nullptr;     // split-K tail of the big GEMMs
   int* tail_counters = nullptr;
   z64* tune_scratch = nullptr; // autotuner output sink (N x ne), allocated on first use
@@ -236,7 +238,7 @@ struct Workspace {
     return kOk;
   }
 
-  int create(int64_t N_, int ne_, bool mixed, bool lanczos) {
+  int create(int64_t N_, int ne_, bool mixed, bool lanczos, bool bf16 = false) {
     N = N_;
     ne = ne_;
     const size_t nne = (size_t)N * ne, sq = (size_t)ne * ne;
@@ -271,6 +273,10 @@ struct Workspace {
       st = st ? st : alloc(&A32, (size_t)N * N);
       st = st ? st : alloc(&X32a, nne);
       st = st ? st : alloc(&X32b, nne);
+    }
+    if (bf16) {
+      ldp = bsplit_ld(N);
+      st = st ? st : alloc(&P16, (size_t)4 * ldp * N);
     }
     if (!st && rocblas_create_handle(&rb) != rocblas_status_success) {
       set_msg("rocblas_create_handle failed");
@@ -418,11 +424,13 @@ static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, in
   return kOk;
 }
 
-// FP32 filter for the columns still in low precision (same recurrence and
-// scalars as run_filter, complex64 data, FP32 accumulation on MFMA).
-static int run_filter_fp32(const c32* A32, int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int64_t n,
-                           const int32_t* degs, double c, double e, double mu1, int64_t* matvecs,
-                           int64_t* launches, hipStream_t s, void* tail_ws, int* tail_counters) {
+// Low-precision filter for the columns still on an FP32 or BF16x3 rung: the
+// same recurrence and scalars as plan_filter, on complex64 copies of the
+// columns (X0/X1 ping-pong), converted back to complex128 as each column
+// reaches its degree.  `launch` runs one step's GEMM.
+static int run_filter_lowp(int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int64_t n, const int32_t* degs,
+                           double c, double e, double mu1, int64_t* matvecs, int64_t* launches, hipStream_t s,
+                           const std::function<int(const CGemmArgs&)>& launch) {
   if (n <= 0) return kOk;
   int st = convert_z_to_c(V, ldv, X0, N, N, n, s);
   if (st) return st;
@@ -434,7 +442,7 @@ static int run_filter_fp32(const c32* A32, int64_t N, z64* V, int64_t ldv, c32* 
   for (int k = 0; k < dmax; ++k) {
     int64_t s0 = 0;
     while (s0 < n && degs[s0] < k + 1) ++s0;
-    // columns that finished after step k (degree == k) are in X0 (k even): convert back
+    // columns that finished after step k (degree == k, even) sit in X0
     if (s0 > done) {
       st = convert_c_to_z(X0 + done * N, N, V + done * ldv, ldv, N, s0 - done, s);
       if (st) return st;
@@ -457,12 +465,11 @@ static int run_filter_fp32(const c32* A32, int64_t N, z64* V, int64_t ldv, c32* 
     c32* out = cur0 ? X1 : X0;
     CGemmArgs g;
     g.M = N; g.N = cols; g.K = N;
-    g.A = A32; g.lda = N;
     g.B = cur + s0 * N; g.ldb = N;
     g.Y = out + s0 * N; g.ldy = N;
     g.Z = cur + s0 * N; g.ldz = N;
     g.alpha = (float)alpha; g.beta = (float)beta; g.gamma = (float)(-alpha * c);
-    st = cfilter_big_launch(g, s, tail_ws, tail_counters);
+    st = launch(g);
     if (st) return st;
     mv += cols;
     ++nl;
@@ -703,7 +710,8 @@ static bool valid_params(const chase_params_t* p) {
   if (p->deg < 2 || p->deg % 2 || p->max_deg < 2 || p->max_deg % 2) return false;
   if (!(p->tol > 0)) return false;
   if (p->max_iter < 1 || p->lanczos_steps < 1 || p->lanczos_steps > 256) return false;
-  if (p->precision != CHASE_FP64 && p->precision != CHASE_FP32_MIXED) return false;
+  if (p->precision != CHASE_FP64 && p->precision != CHASE_FP32_MIXED && p->precision != CHASE_BF16X3_MIXED)
+    return false;
   if (p->force_qr < -1 || p->force_qr > 3) return false;
   return true;
 }
@@ -724,10 +732,10 @@ struct ProblemState {
   bool mixed = false;
   std::vector<int32_t> degs;
   std::vector<double> Lam, resd, prev_resd, th_h, rs_h;
-  std::vector<char> low;  // column still filtered in FP32 (mixed precision)
+  std::vector<char> low;  // precision rung of each column: 2 BF16x3, 1 FP32, 0 FP64
   int locked = 0, it = 1;
   double bnd[4] = {0, 0, 0, 0};
-  double b_sup = 0, mu_ne = 0, c = 0, e = 1, mu1_cur = 0, tol_abs = 0, sw_abs = 0;
+  double b_sup = 0, mu_ne = 0, c = 0, e = 1, mu1_cur = 0, tol_abs = 0, sw_abs = 0, sw16_abs = 0;
   bool breakdown = false;
   chase_stats_t S{};
   int64_t total_mv = 0;
@@ -767,7 +775,7 @@ struct ProblemState {
     N = w->N;
     nev = P.nev;
     ne = P.nev + P.nex;
-    mixed = P.precision == CHASE_FP32_MIXED;
+    mixed = P.precision != CHASE_FP64;
     std::memset(&S, 0, sizeof(S));
     if (!use_v0 && (st = fill_gaussian(V, ldv, N, ne, P.seed, s))) return st;
     if (P.bounds_given) {
@@ -794,14 +802,16 @@ struct ProblemState {
     mu_ne = bnd[2];
     tol_abs = P.tol * bnd[3];
     sw_abs = P.mixed_switch * bnd[3];
+    sw16_abs = P.bf16_switch * bnd[3];
     c = 0.5 * (b_sup + mu_ne);
     e = 0.5 * (b_sup - mu_ne);
     if (mixed && (st = convert_z_to_c(A, lda, w->A32, N, N, N, s))) return st;
+    if (P.precision == CHASE_BF16X3_MIXED && (st = bsplit_planes(A, lda, N, w->P16, s))) return st;
     degs.assign(ne, P.deg);
     Lam.assign(ne, 0.0);
     resd.assign(ne, std::numeric_limits<double>::infinity());
     prev_resd = resd;
-    low.assign(ne, mixed ? 1 : 0);
+    low.assign(ne, (char)P.precision);
     th_h.assign(ne, 0.0);
     rs_h.assign(ne, 0.0);
     return copy_columns(V, ldv, w->C2, N, N, ne, s);
@@ -832,11 +842,13 @@ struct ProblemState {
     return kOk;
   }
 
-  int n_low() const {
+  // active columns on rung r (contiguous: the sort puts higher rungs first)
+  int n_rung(int r) const {
     int k = 0;
-    while (k < na() && low[locked + k]) ++k;
+    for (int j = 0; j < na(); ++j) k += (low[locked + j] == r);
     return k;
   }
+  int n_low() const { return n_rung(1) + n_rung(2); }
 
   // FP64 filter GEMMs of this iteration (the columns not in FP32).
   std::vector<GemmArgs> plan() {
@@ -850,12 +862,43 @@ struct ProblemState {
     t_f.start(s);
     int st = kOk;
     int64_t mv = 0, nl = 0;
-    const int nlow = mixed ? n_low() : 0;
-    if (nlow > 0) {
+    const int n16 = mixed ? n_rung(2) : 0, n32 = mixed ? n_rung(1) : 0;
+    if (n16 > 0) {
+      int64_t mv16 = 0, nl16 = 0;
+      const uint16_t* P16 = w->P16;
+      const int64_t ldp = w->ldp;
+      void* tw = w->tail_ws;
+      int* tc = w->tail_counters;
+      auto launch = [&](const CGemmArgs& a) {
+        BGemmArgs b;
+        b.M = a.M; b.N = a.N; b.K = a.K;
+        b.P = P16; b.ldp = ldp; b.plane_stride = ldp * N;
+        b.X = a.B; b.ldx = a.ldb;
+        b.Y = a.Y; b.ldy = a.ldy;
+        b.Z = a.Z; b.ldz = a.ldz;
+        b.alpha = a.alpha; b.beta = a.beta; b.gamma = a.gamma;
+        return bfilter_launch(b, s, tw, tc);
+      };
+      if ((st = run_filter_lowp(N, V + (int64_t)locked * ldv, ldv, w->X32a, w->X32b, n16, degs.data() + locked,
+                                c, e, mu1_cur, &mv16, &nl16, s, launch)))
+        return st;
+      S.filter_matvecs_bf16 += mv16;
+      mv += mv16;
+      nl += nl16;
+    }
+    if (n32 > 0) {
       int64_t mv32 = 0, nl32 = 0;
-      if ((st = run_filter_fp32(w->A32, N, V + (int64_t)locked * ldv, ldv, w->X32a, w->X32b, nlow,
-                                degs.data() + locked, c, e, mu1_cur, &mv32, &nl32, s, w->tail_ws,
-                                w->tail_counters)))
+      const c32* A32 = w->A32;
+      void* tw = w->tail_ws;
+      int* tc = w->tail_counters;
+      auto launch = [&](const CGemmArgs& a) {
+        CGemmArgs b = a;
+        b.A = A32;
+        b.lda = N;
+        return cfilter_big_launch(b, s, tw, tc);
+      };
+      if ((st = run_filter_lowp(N, V + (int64_t)(locked + n16) * ldv, ldv, w->X32a, w->X32b, n32,
+                                degs.data() + locked + n16, c, e, mu1_cur, &mv32, &nl32, s, launch)))
         return st;
       S.filter_matvecs_fp32 += mv32;
       mv += mv32;
@@ -907,9 +950,12 @@ struct ProblemState {
       if (!std::isfinite(th_h[j]) || !std::isfinite(rs_h[j])) breakdown = true;
     }
     if (breakdown) return kOk;
-    if (mixed)  // a column leaves FP32 once at the FP32 floor or no longer improving
-      for (int j = locked; j < ne; ++j)
-        if (low[j] && (resd[j] <= sw_abs || resd[j] > 0.5 * prev_resd[j])) low[j] = 0;
+    if (mixed)  // a column moves down a rung at the rung's floor or once it stops improving
+      for (int j = locked; j < ne; ++j) {
+        const bool stalled = resd[j] > 0.5 * prev_resd[j];
+        if (low[j] == 2 && (resd[j] <= sw16_abs || stalled)) low[j] = 1;
+        else if (low[j] == 1 && (resd[j] <= sw_abs || stalled)) low[j] = 0;
+      }
 
     // Deflation and locking
     std::vector<int> order;
@@ -1007,6 +1053,7 @@ int chase_default_params(chase_params_t* p) {
   p->bounds_given = 0;
   p->tol = 1e-10;
   p->mixed_switch = 1e-6;
+  p->bf16_switch = 1e-4;
   p->seed = 2309;
   return 0;
 }
@@ -1017,7 +1064,8 @@ int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h) {
   if (!h) return -3;
   auto* hh = new chase_handle_s();
   hh->p = *p;
-  int st = hh->w.create(N, p->nev + p->nex, p->precision == CHASE_FP32_MIXED, true);
+  int st = hh->w.create(N, p->nev + p->nex, p->precision != CHASE_FP64, true,
+                        p->precision == CHASE_BF16X3_MIXED);
   if (st) {
     delete hh;
     *h = nullptr;

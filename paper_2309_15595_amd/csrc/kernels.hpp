@@ -77,6 +77,21 @@ struct CGemmArgs {
 // the FP64 one, on complex64 data with FP32 accumulation.
 int cfilter_big_launch(const CGemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters);
 
+// BF16x3 filter step (bfilter.hip): H as four bfloat16 planes (Re hi, Re lo,
+// Im hi, Im lo of conj(H) in H's memory order, rows padded to ldp), X, Y, Z
+// complex64.
+struct BGemmArgs {
+  int64_t M = 0, N = 0, K = 0;
+  const uint16_t* P = nullptr; int64_t ldp = 0; int64_t plane_stride = 0;
+  const c32* X = nullptr; int64_t ldx = 0;
+  c32* Y = nullptr;       int64_t ldy = 0;
+  const c32* Z = nullptr; int64_t ldz = 0;
+  float alpha = 1.f, beta = 0.f, gamma = 0.f;
+};
+int64_t bsplit_ld(int64_t N);
+int bsplit_planes(const z64* H, int64_t lda, int64_t N, uint16_t* P, hipStream_t s);
+int bfilter_launch(const BGemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters);
+
 // ---- small dense kernels (small.hip) --------------------------------------
 // Blocked lower Cholesky G = L L^H in place (lower part), n x n, ld.
 // *info (device) receives 0, or j+1 for the first non-positive pivot j.

@@ -41,10 +41,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     L = _lib()
-    # chase_params_t: 12 int32 + 6 double + uint64
-    assert ctypes.sizeof(L.chase_params_t) == 12 * 4 + 6 * 8 + 8
-    # chase_stats_t: 8 int32 + 4 int64 + 7 double + 4 double
-    assert ctypes.sizeof(L.chase_stats_t) == 8 * 4 + 4 * 8 + 7 * 8 + 4 * 8
+    # chase_params_t: 12 int32 + 7 double + uint64
+    assert ctypes.sizeof(L.chase_params_t) == 12 * 4 + 7 * 8 + 8
+    # chase_stats_t: 8 int32 + 5 int64 + 7 double + 4 double
+    assert ctypes.sizeof(L.chase_stats_t) == 8 * 4 + 5 * 8 + 7 * 8 + 4 * 8
 
 
 def test_default_params_host_only():
@@ -89,3 +89,22 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.chase_eigval_grad(10, 0, None, 10, None, None, 10, 0, None) == -2
     assert lib.chase_filter(None, 10, None, 10, None, 10, 10, 1, None, 0.0, 1.0, -1.0, None, None) == -1
     assert np.isnan(L.chase_cond_est([1.0], 0.0, 0.0, [2], 0))
+
+
+def test_struct_sizes_match_c_compiler(tmp_path):
+    """sizeof of the C structs (compiled from the header with the host C
+    compiler) equals the ctypes mirrors."""
+    import shutil
+    import subprocess
+    L = _lib()
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "chase_hip.h"\n'
+                   'int main(void){printf("%zu %zu\\n", sizeof(chase_params_t), sizeof(chase_stats_t));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert int(out[0]) == ctypes.sizeof(L.chase_params_t)
+    assert int(out[1]) == ctypes.sizeof(L.chase_stats_t)

@@ -87,21 +87,27 @@ def test_batched_rejects_mixed_precision(L):
 
 # ---------------------------------------------------------------- mixed precision
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("N,nev,nex,spectrum", [(800, 60, 20, "uniform"), (1200, 60, 15, "dft")])
-def test_mixed_precision_reaches_fp64_accuracy(L, N, nev, nex, spectrum):
+def test_mixed_precision_reaches_fp64_accuracy(L, N, nev, nex, spectrum, prec):
     from paper_2309_15595_amd.api import Solver
     p = synth.make_problem(N, nev, nex, spectrum=spectrum, basis="gaussian", seed=N + 7)
-    with Solver(N, nev, nex, precision=L.CHASE_FP32_MIXED) as s:
+    code = L.CHASE_FP32_MIXED if prec == "fp32" else L.CHASE_BF16X3_MIXED
+    with Solver(N, nev, nex, precision=code) as s:
         Vd = cm(p.V0)
         ritz, resid, info = s.solve_colmajor(cm(p.A), Vd, True, cm(p.starts))
     assert info.converged, info.stats
     X = un(Vd)[:, :nev]
     ref = oc.chase(p.A, oc.Params(nev=nev, nex=nex), V0=p.V0, starts=p.starts)
     err = np.abs(ritz - ref.evals) / p.norm2
-    print(f"\nmixed: max per-eigenpair |d lambda|/||A|| vs FP64 oracle = {err.max():.2e}; "
-          f"FP32 MatVec share {info.stats['filter_matvecs_fp32'] / info.stats['filter_matvecs']:.2f}")
+    st = info.stats
+    print(f"\nmixed {prec}: max per-eigenpair |d lambda|/||A|| vs FP64 oracle = {err.max():.2e}; "
+          f"MatVec shares FP32 {st['filter_matvecs_fp32'] / st['filter_matvecs']:.2f}, "
+          f"BF16x3 {st['filter_matvecs_bf16'] / st['filter_matvecs']:.2f}")
     assert err.max() <= 1e-10
-    assert info.stats["filter_matvecs_fp32"] > 0
+    assert st["filter_matvecs_fp32"] > 0
+    if prec == "bf16x3":
+        assert st["filter_matvecs_bf16"] > 0
     r_true = np.linalg.norm(p.A @ X - X * ritz, axis=0)
     assert np.max(r_true) <= 1e-10 * p.norm2 * (1 + 1e-6)
     assert np.linalg.norm(X.conj().T @ X - np.eye(nev), 2) <= 1e-12
