@@ -67,32 +67,6 @@ __device__ __forceinline__ bool map_tile(int64_t ntiles, int64_t tiles_n, int64_
   return true;
 }
 
-#ifndef ZF_GROUP_M
-#define ZF_GROUP_M 0
-#endif
-#ifndef ZF_PREFETCH2
-#define ZF_PREFETCH2 0
-#endif
-
-// Row panels are split evenly over the 8 XCDs; within an XCD, tiles are
-// walked in groups of GM row panels, column tile by column tile, so that
-// co-running workgroups share both H panels and X column tiles in L2.
-// Returns false for padding blocks.  Grid: 8 * tiles_per_xcd_max.
-__device__ __forceinline__ bool map_tile_grouped(int64_t tiles_m, int64_t tiles_n, int GM, int64_t& tm,
-                                                 int64_t& tn) {
-  const int64_t bid = blockIdx.x;
-  const int64_t x = bid % 8, i = bid / 8;
-  const int64_t p0 = x * tiles_m / 8, p1 = (x + 1) * tiles_m / 8;  // row panels of this XCD
-  const int64_t np = p1 - p0;
-  if (i >= np * tiles_n) return false;
-  const int64_t gsz = (int64_t)GM * tiles_n;
-  const int64_t g = i / gsz, r = i % gsz;
-  const int64_t rows = (np - g * GM) < GM ? (np - g * GM) : GM;  // panels in this group
-  tn = r / rows;
-  tm = p0 + g * GM + r % rows;
-  return true;
-}
-
 template <int WGM, int WGN, int TM, int TN, int BK>
 struct Cfg {
   static constexpr int NT = 64 * WGM * WGN;
@@ -184,30 +158,11 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
   };
 
   const int64_t nkt = (kend - kbeg + BK - 1) / BK;
-#if ZF_PREFETCH2
-  // two register sets: tile t+2 is loaded two K-tiles before it is stored
-  zv ra2[LA], rb2[LB];
-  auto swap_sets = [&]() {
-#pragma unroll
-    for (int r = 0; r < LA; ++r) { zv x = ra[r]; ra[r] = ra2[r]; ra2[r] = x; }
-#pragma unroll
-    for (int r = 0; r < LB; ++r) { zv x = rb[r]; rb[r] = rb2[r]; rb2[r] = x; }
-  };
-  if (nkt > 0) {
-    gload(kbeg);
-    sstore(0);
-    if (nkt > 1) gload(kbeg + BK);       // tile 1 -> (ra, rb)
-    swap_sets();                          // tile 1 -> (ra2, rb2)
-    if (nkt > 2) gload(kbeg + 2 * BK);   // tile 2 -> (ra, rb)
-    // the loop swaps first: (ra, rb) must hold tile 2 and (ra2, rb2) tile 1 here
-  }
-#else
   if (nkt > 0) {
     gload(kbeg);
     sstore(0);
     if (nkt > 1) gload(kbeg + BK);
   }
-#endif
   __syncthreads();
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int buf = (int)(kt & 1);
@@ -242,19 +197,10 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
           ci[nb][mb] = P::mma(bi[nb], ar[mb], ci[nb][mb]);
         }
     }
-#if ZF_PREFETCH2
-    // invariant at the top of iteration kt: (ra2, rb2) = tile kt+1, (ra, rb) = tile kt+2
-    if (kt + 1 < nkt) {
-      swap_sets();            // (ra, rb) = tile kt+1, (ra2, rb2) = tile kt+2
-      sstore(buf ^ 1);
-      if (kt + 3 < nkt) gload(kbeg + (kt + 3) * BK);  // (ra, rb) = tile kt+3
-    }
-#else
     if (kt + 1 < nkt) {
       sstore(buf ^ 1);
       if (kt + 2 < nkt) gload(kbeg + (kt + 2) * BK);
     }
-#endif
     __syncthreads();
   }
 
@@ -328,15 +274,7 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& ta
   const int64_t grid_main = 8 * ((tail.full + 7) / 8);
   if ((int64_t)blockIdx.x < grid_main) {
     int64_t tm, tn;
-#if ZF_GROUP_M > 0
-    if (tail.ksplit == 1) {  // whole launch: grouped order over all row panels
-      if (!map_tile_grouped((g.M + BM - 1) / BM, tiles_n, ZF_GROUP_M, tm, tn)) return;
-    } else if (!map_tile(tail.full, tiles_n, tm, tn)) {
-      return;
-    }
-#else
     if (!map_tile(tail.full, tiles_n, tm, tn)) return;
-#endif
     zbig_tile<P, WGM, WGN, TM, TN, BK>(g, tm, tn, s);
     return;
   }
@@ -510,10 +448,7 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
   t.counters = tail_counters;
   const int64_t nkt = cdiv(g.K, c.bk);
   const int64_t rem = tiles % G;
-  bool use_tail = tail_ws && tail_counters && rem > 0 && choice != kChoiceT0NoTail;
-#ifdef ZF_NO_TAIL
-  use_tail = false;
-#endif
+  const bool use_tail = tail_ws && tail_counters && rem > 0 && choice != kChoiceT0NoTail;
   if (use_tail) {
     // split the last round's tiles along K to fill the idle CUs: minimise
     // ceil(rem * s / G) / s (in units of one tile's time)
@@ -532,12 +467,7 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
       t.ksplit = best;
     }
   }
-  int64_t grid = 8 * cdiv(t.full, 8) + (tiles - t.full) * t.ksplit;
-#if ZF_GROUP_M > 0
-  if (t.ksplit == 1) {  // grouped order: 8 x (most panels on one XCD x column tiles)
-    grid = 8 * (cdiv(cdiv(g.M, c.bm), 8) * cdiv(g.N, c.bn));
-  }
-#endif
+  const int64_t grid = 8 * cdiv(t.full, 8) + (tiles - t.full) * t.ksplit;
   GemmArgs a = g;
   if (a.K <= 0) a.alpha = 0.0;
   if (!filter_symbol)
