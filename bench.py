@@ -82,7 +82,7 @@ def cpu_baseline(A_host, V0, args):
         cores = max(int(i.get("num_threads", 0)) for i in threadpool_info()) or os.cpu_count()
     except Exception:
         cores = len(os.sched_getaffinity(0))
-    n_s, deg = 128, 2
+    n_s, deg = 256, 20   # about 16 TFLOP: 10-30 s on a host of 8-16 cores
     X = np.ascontiguousarray(V0[:, :n_s])
     oc.chebyshev_filter(A_host, X[:, :8], np.full(8, 2), 0.5, 5.0, -1.0)  # BLAS warm-up
     t0 = time.perf_counter()
