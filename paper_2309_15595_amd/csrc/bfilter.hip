@@ -25,6 +25,7 @@
 // was measured on gfx950.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "sched.hpp"
 
 namespace chase {
 
@@ -52,15 +53,6 @@ struct BSmem {
 
 __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
 
-__device__ __forceinline__ bool map_tile(int64_t ntiles, int64_t tiles_n, int64_t& tm, int64_t& tn) {
-  const int64_t bid = blockIdx.x;
-  const int64_t per = (ntiles + 7) / 8;
-  const int64_t tile = (bid % 8) * per + bid / 8;
-  if (tile >= ntiles) return false;
-  tm = tile / tiles_n;
-  tn = tile % tiles_n;
-  return true;
-}
 
 // One 128 x 128 output tile over K range [kbeg, kend) (multiples of BK, kend
 // may exceed K: the planes are zero-padded and X loads are guarded).
@@ -68,15 +60,14 @@ template <bool EDGE>
 __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg, int64_t kend,
                                       cv* part, BSmem& s) {
   const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wm = wave & 1, wn = wave >> 1;
   const int l16 = lane & 15, kq = lane >> 4;
-  int vmb = TM, vnb = TN;
-  if (EDGE) {
-    const int64_t rm = g.M - (m0 + wm * 64), rn = g.N - (n0 + wn * 32);
-    vmb = (int)(rm <= 0 ? 0 : (rm >= 64 ? TM : (rm + 15) / 16));
-    vnb = (int)(rn <= 0 ? 0 : (rn >= 32 ? TN : (rn + 15) / 16));
-  }
+  // EDGE tiles: a wave whose 64 x 32 sub-tile lies wholly outside the output
+  // skips its fragment reads and MFMAs; one that touches it computes the
+  // whole sub-tile on the zero-padded operands.  The test is a single
+  // wave-uniform branch per K-tile, so the MFMA stream is never split.
+  const bool active = !EDGE || (m0 + wm * 64 < g.M && n0 + wn * 32 < g.N);
   f32x4 rp[TN][TM], rn_[TN][TM], im[TN][TM];
 #pragma unroll
   for (int a = 0; a < TN; ++a)
@@ -139,31 +130,32 @@ __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn
   __syncthreads();
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int buf = (int)(kt & 1);
-    bf16x8 xf[TN][4];
+    if (active) {
+      bf16x8 xf[TN][4];
 #pragma unroll
-    for (int nb = 0; nb < TN; ++nb) {
-      const int n = wn * 32 + nb * 16 + l16;
+      for (int nb = 0; nb < TN; ++nb) {
+        const int n = wn * 32 + nb * 16 + l16;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const uint4 w = s.x[buf][p][n][swz(n, kq)];
-        xf[nb][p] = __builtin_bit_cast(bf16x8, w);
+        for (int p = 0; p < 4; ++p) {
+          const uint4 w = s.x[buf][p][n][swz(n, kq)];
+          xf[nb][p] = __builtin_bit_cast(bf16x8, w);
+        }
       }
-    }
 #pragma unroll
-    for (int mb = 0; mb < TM; ++mb) {
-      if (EDGE && mb >= vmb) continue;
-      const int m = wm * 64 + mb * 16 + l16;
-      bf16x8 hf[4];
+      for (int mb = 0; mb < TM; ++mb) {
+        const int m = wm * 64 + mb * 16 + l16;
+        bf16x8 hf[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) hf[p] = __builtin_bit_cast(bf16x8, s.h[buf][p][m][swz(m, kq)]);
-      // planes: 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo
+        for (int p = 0; p < 4; ++p) hf[p] = __builtin_bit_cast(bf16x8, s.h[buf][p][m][swz(m, kq)]);
+        // planes: 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo
 #define BMMA(acc, xp, hp)                                                                   \
-  _Pragma("unroll") for (int nb = 0; nb < TN; ++nb) if (!EDGE || nb < vnb)                  \
+  _Pragma("unroll") for (int nb = 0; nb < TN; ++nb)                                        \
       acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xf[nb][xp], hf[hp], acc[nb][mb], 0, 0, 0);
-      BMMA(rp, 0, 0) BMMA(rn_, 2, 2) BMMA(im, 0, 2) BMMA(im, 2, 0)
-      BMMA(rp, 0, 1) BMMA(rn_, 2, 3) BMMA(im, 0, 3) BMMA(im, 2, 1)
-      BMMA(rp, 1, 0) BMMA(rn_, 3, 2) BMMA(im, 1, 2) BMMA(im, 3, 0)
+        BMMA(rp, 0, 0) BMMA(rn_, 2, 2) BMMA(im, 0, 2) BMMA(im, 2, 0)
+        BMMA(rp, 0, 1) BMMA(rn_, 2, 3) BMMA(im, 0, 3) BMMA(im, 2, 1)
+        BMMA(rp, 1, 0) BMMA(rn_, 3, 2) BMMA(im, 1, 2) BMMA(im, 3, 0)
 #undef BMMA
+      }
     }
     if (kt + 1 < nkt) {
       sstore(buf ^ 1);
@@ -219,33 +211,14 @@ __device__ __forceinline__ void btile_any(const BGemmArgs& g, int64_t tm, int64_
     btile<true>(g, tm, tn, kbeg, kend, part, s);
 }
 
-__global__ __launch_bounds__(NT, 1) void bfilter_step(BGemmArgs g, TailSplit tail) {
-  __shared__ BSmem s;
-  __shared__ int last;
-  const int64_t kpad = (g.K + BK - 1) / BK * BK;
-  const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const int64_t grid_main = 8 * ((tail.full + 7) / 8);
-  if ((int64_t)blockIdx.x < grid_main) {
-    int64_t tm, tn;
-    if (!map_tile(tail.full, tiles_n, tm, tn)) return;
-    btile_any(g, tm, tn, 0, kpad, nullptr, s);
-    return;
-  }
-  const int64_t j = (int64_t)blockIdx.x - grid_main;
-  const int64_t tl = j / tail.ksplit, sp = j % tail.ksplit;
-  const int64_t tile = tail.full + tl;
-  const int64_t tm = tile / tiles_n, tn = tile % tiles_n;
-  const int64_t nkt = kpad / BK;
-  const int64_t per = (nkt + tail.ksplit - 1) / tail.ksplit;
-  const int64_t kbeg = sp * per * BK;
-  const int64_t kend = (sp + 1) * per * BK < kpad ? (sp + 1) * per * BK : kpad;
-  cv* part = reinterpret_cast<cv*>(tail.ws) + j * (int64_t)(BM * BN);
-  btile_any(g, tm, tn, kbeg, kend, part, s);
+// A segment has stored its partial tile: count it in; the last segment of a
+// tile to arrive sums the partials in segment order and applies the epilogue.
+__device__ __forceinline__ void barrive(const BGemmArgs& g, const TailSplit& tail, const WorkItem& w,
+                                        int64_t tiles_n, int* last) {
+  const int64_t tl = w.seg / tail.ksplit;
+  const int64_t tm = w.tile / tiles_n, tn = w.tile % tiles_n;
   __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(tail.counters + tl, 1) == tail.ksplit - 1);
-  __syncthreads();
-  if (!last) return;
+  if (wg_fetch_add(tail.counters + tl, 1, last) != tail.ksplit - 1) return;
   __threadfence();
   const cv* parts = reinterpret_cast<const cv*>(tail.ws) + tl * tail.ksplit * (int64_t)(BM * BN);
   cv* Y = reinterpret_cast<cv*>(g.Y);
@@ -274,6 +247,22 @@ __global__ __launch_bounds__(NT, 1) void bfilter_step(BGemmArgs g, TailSplit tai
     Y[m + n * g.ldy] = out;
   }
   if (threadIdx.x == 0) tail.counters[tl] = 0;
+}
+
+// Persistent grid on the per-XCD work queue (sched.hpp).
+__global__ __launch_bounds__(NT, 1) void bfilter_step(BGemmArgs g, TailSplit tail) {
+  __shared__ BSmem s;
+  __shared__ int last, item;
+  const int64_t kpad = (g.K + BK - 1) / BK * BK;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const QueueShare q = queue_share(tail, ((g.M + BM - 1) / BM) * tiles_n);
+  for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
+    const WorkItem w = work_item(tail, i, kpad, BK);
+    cv* part = w.seg < 0 ? nullptr : reinterpret_cast<cv*>(tail.ws) + w.seg * (int64_t)(BM * BN);
+    btile_any(g, w.tile / tiles_n, w.tile % tiles_n, w.kbeg, w.kend, part, s);
+    if (w.seg >= 0) barrive(g, tail, w, tiles_n, &last);
+  }
+  queue_leave(tail);
 }
 
 // conj(H) split into Re hi/lo and Im hi/lo bfloat16 planes, rows padded.
@@ -325,31 +314,11 @@ int bsplit_planes(const z64* H, int64_t lda, int64_t N, uint16_t* P, hipStream_t
 
 int bfilter_launch(const BGemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters) {
   if (g.M <= 0 || g.N <= 0) return kOk;
-  const int64_t tiles = cdiv(g.M, BM) * cdiv(g.N, BN);
-  const int64_t G = cu_count_b();
+  if (!tail_ws || !tail_counters) return -1;
+  TileGeom geo;  // 8 waves of 64 x 32: wave w at (w & 1, w >> 1)
+  geo.M = g.M; geo.N = g.N; geo.bm = BM; geo.bn = BN; geo.wgm = 2; geo.wgn = 4;
   TailSplit t;
-  t.full = tiles;
-  t.ws = tail_ws;
-  t.counters = tail_counters;
-  const int64_t nkt = cdiv(g.K, BK);
-  const int64_t rem = tiles % G;
-  if (tail_ws && tail_counters && rem > 0) {
-    int best = 1;
-    double cost_best = 1.0;
-    for (int sp = 2; sp <= 8; ++sp) {
-      if (nkt < 8 * sp || rem * sp > kTailMaxSegments) break;
-      const double cost = (double)cdiv(rem * sp, G) / sp;
-      if (cost < cost_best - 1e-9) {
-        cost_best = cost;
-        best = sp;
-      }
-    }
-    if (best > 1) {
-      t.full = tiles - rem;
-      t.ksplit = best;
-    }
-  }
-  const int64_t grid = 8 * cdiv(t.full, 8) + (tiles - t.full) * t.ksplit;
+  const int64_t grid = plan_schedule(geo, cdiv(g.K, BK), cu_count_b(), 8, true, tail_ws, tail_counters, &t);
   hipLaunchKernelGGL(bfilter_step, dim3((unsigned)grid), dim3(NT), 0, s, g, t);
   CHASE_CHK_LAUNCH();
   return kOk;

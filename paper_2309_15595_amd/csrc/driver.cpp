@@ -258,7 +258,7 @@ struct Workspace {
     st = st ? st : alloc(&flag, 1);
     st = st ? st : alloc(&perm, (size_t)ne);
     st = st ? st : alloc(reinterpret_cast<char**>(&tail_ws), (size_t)tail_workspace_bytes());
-    st = st ? st : alloc(&tail_counters, (size_t)kTailMaxSegments);
+    st = st ? st : alloc(&tail_counters, (size_t)kTailCounterInts);
     if (!st) st = tail_counters_init(tail_counters, nullptr);
     if (!st && hipDeviceSynchronize() != hipSuccess) st = kHipError;
     st = st ? st : alloc(&lz_alpha, 8 * 256);
@@ -1383,7 +1383,7 @@ int chase_filter(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int6
   void* tws = nullptr;
   int* tcnt = nullptr;
   if (hipMalloc(&tws, (size_t)tail_workspace_bytes()) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&tcnt), sizeof(int) * kTailMaxSegments) != hipSuccess) {
+      hipMalloc(reinterpret_cast<void**>(&tcnt), sizeof(int) * kTailCounterInts) != hipSuccess) {
     (void)hipGetLastError();
     if (tws) (void)hipFree(tws);
     return kAllocFailed;

@@ -20,28 +20,53 @@ struct GemmArgs {
 };
 
 // opa/opb: 0 = as stored, 1 = conjugate transpose.
-int zgemm_launch(int opa, int opb, const GemmArgs& g, hipStream_t s, bool filter_symbol = false);
-// Split of the last, partial round of tiles along K (see zfilter.hip).
+int zgemm_launch(int opa, int opb, const GemmArgs& g, hipStream_t s);
+// Schedule of the large tiled products (see sched.hpp): whole tiles plus the
+// last, partial round of tiles split along K, handed out by per-XCD work
+// queues to a persistent grid.
 constexpr int kTailMaxSegments = 1024;
+constexpr int kQueueInts = 16;  // 8 per-XCD item counters, a finished-workgroup count, spare
+// ints of the counter block: kTailMaxSegments arrival counters + the queue
+constexpr int kTailCounterInts = kTailMaxSegments + kQueueInts;
 struct TailSplit {
-  int64_t full = 0;        // tiles computed whole, one workgroup each
+  int64_t full = 0;        // tiles computed whole
   int64_t ksplit = 1;      // K segments per remaining tile
   void* ws = nullptr;      // kTailMaxSegments partial tiles
   int* counters = nullptr; // kTailMaxSegments arrival counters, zero between launches
+  int* queue = nullptr;    // kQueueInts queue counters, zero between launches
 };
+// Output tiling of one launch, for the schedule's cost model: bm x bn tiles
+// of an M x N output, each computed by wgm x wgn waves (wave w owns sub-tile
+// (w % wgm, w / wgm)); on gfx950 waves w and w + 4 of a workgroup share a
+// SIMD.
+struct TileGeom {
+  int64_t M = 0, N = 0;
+  int bm = 128, bn = 128, wgm = 2, wgn = 4;
+};
+// Split and grid of one launch of `nkt` K-tiles per tile with `resident`
+// workgroups resident at once (schedule.cpp).  Candidate splits of the last
+// round(s) of tiles along K (segments of at least min_kt_per_seg K-tiles) are
+// compared by simulating the per-XCD queues with a per-tile cost (a tile
+// costs its busiest SIMD's share of MFMA work: an edge tile whose live
+// columns fit in the first half of the waves costs half a tile).
+// counters: kTailCounterInts ints.  Returns the grid.
+int64_t plan_schedule(const TileGeom& geo, int64_t nkt, int64_t resident, int min_kt_per_seg, bool allow_split,
+                      void* ws, int* counters, TailSplit* t);
 int64_t tail_workspace_bytes();
 int tail_counters_init(int* counters, hipStream_t s);
 // Large NN products (filter step, H C): 128 x 128 tiles, double-buffered LDS
-// (zfilter.hip).  filter_symbol selects the kernel name reported by profilers.
-// With a tail workspace the last partial round of tiles is split along K.
-// choice (filter only): tile configuration and tail policy picked by the
-// autotuner.
+// (zfilter.hip), on the persistent work-queue schedule of plan_schedule; the
+// last partial round of tiles is split along K.  tail_ws / tail_counters
+// (tail_workspace_bytes(), kTailCounterInts ints, zeroed once by
+// tail_counters_init) are required and serialise launches that share them.
+// filter_symbol selects the kernel name reported by profilers.  choice
+// (filter only): tile configuration and tail policy picked by the autotuner.
 constexpr int kChoiceT0Tail = 0;    // 128 x 128, split-K tail
 constexpr int kChoiceT0NoTail = 1;  // 128 x 128, no tail split
 constexpr int kChoiceT1Tail = 2;    // 128 x 64, split-K tail
 constexpr int kNumChoices = 3;
-int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws = nullptr,
-                        int* tail_counters = nullptr, int choice = kChoiceT0Tail);
+int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws, int* tail_counters,
+                        int choice = kChoiceT0Tail);
 // One problem's filter GEMM in a grouped launch: tiles [tile_end - tiles,
 // tile_end) of the step's running tile count belong to it.
 struct GroupEntry {

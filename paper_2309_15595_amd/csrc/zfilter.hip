@@ -21,6 +21,7 @@
 // column of the column-major output.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "sched.hpp"
 
 
 namespace chase {
@@ -57,20 +58,11 @@ struct PF32 {
   static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
 };
 
-__device__ __forceinline__ bool map_tile(int64_t ntiles, int64_t tiles_n, int64_t& tm, int64_t& tn) {
-  const int64_t bid = blockIdx.x;
-  const int64_t per = (ntiles + 7) / 8;
-  const int64_t tile = (bid % 8) * per + bid / 8;
-  if (tile >= ntiles) return false;
-  tm = tile / tiles_n;
-  tn = tile % tiles_n;
-  return true;
-}
-
 template <int WGM, int WGN, int TM, int TN, int BK>
 struct Cfg {
   static constexpr int NT = 64 * WGM * WGN;
   static constexpr int BK_ = BK;
+  static constexpr int WGM_ = WGM, WGN_ = WGN;
   static constexpr int BM = WGM * TM * 16;
   static constexpr int BN = WGN * TN * 16;
   static constexpr int APAD = BM + 2;
@@ -87,9 +79,13 @@ struct Smem {
   typename P::real b[2][2][BK][C::BPAD];  // [buffer][re/im][k][n]
 };
 
-// One BM x BN output tile (tm, tn) of g.  EDGE tiles overhang the output:
-// MFMA blocks of a wave that lie wholly outside it are skipped (the padded
-// columns of the last column tile are most of its work when n_act is small).
+// One BM x BN output tile (tm, tn) of g.  EDGE tiles overhang the output: a
+// wave whose sub-tile lies wholly outside it skips its fragment reads and
+// MFMAs (the padded columns of the last column tile are most of its work
+// when n_act is small); a wave that touches the output computes its whole
+// sub-tile on the zero-filled operands.  The test is one branch per K-tile on
+// a wave-uniform (scalar) value: a per-block test would split the MFMA stream
+// into exec-masked basic blocks and stall the matrix pipe.
 //
 // kbeg/kend (multiples of BK) restrict the K range; with part != nullptr the
 // raw accumulator tile is stored there (tile-local, m fastest) instead of
@@ -105,16 +101,11 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
   constexpr int NT = C::NT, BM = C::BM, BN = C::BN, LA = C::LA, LB = C::LB;
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
+  const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wm = wave % WGM, wn = wave / WGM;
   const int l16 = lane & 15, kq = lane >> 4;
-  // 16-blocks of this wave that touch the output (uniform across the wave)
-  int vmb = TM, vnb = TN;
-  if (EDGE) {
-    const int64_t rm = g.M - (m0 + wm * TM * 16), rn = g.N - (n0 + wn * TN * 16);
-    vmb = (int)(rm <= 0 ? 0 : (rm >= TM * 16 ? TM : (rm + 15) / 16));
-    vnb = (int)(rn <= 0 ? 0 : (rn >= TN * 16 ? TN : (rn + 15) / 16));
-  }
+  // does this wave's sub-tile touch the output? (wave-uniform)
+  const bool active = !EDGE || (m0 + wm * TM * 16 < g.M && n0 + wn * TN * 16 < g.N);
 
   accv cr[TN][TM], ci[TN][TM];
 #pragma unroll
@@ -166,36 +157,36 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
   __syncthreads();
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int buf = (int)(kt & 1);
+    if (active) {
 #pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int kk = ks * 4 + kq;
-      real br[TN], bi[TN], ar[TM], ai[TM];
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kk = ks * 4 + kq;
+        real br[TN], bi[TN], ar[TM], ai[TM];
 #pragma unroll
-      for (int i = 0; i < TN; ++i) {
-        br[i] = s.b[buf][0][kk][wn * TN * 16 + i * 16 + l16];
-        bi[i] = s.b[buf][1][kk][wn * TN * 16 + i * 16 + l16];
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        ar[i] = s.a[buf][0][kk][wm * TM * 16 + i * 16 + l16];
-        ai[i] = s.a[buf][1][kk][wm * TM * 16 + i * 16 + l16];
-      }
-#pragma unroll
-      for (int nb = 0; nb < TN; ++nb)
-#pragma unroll
-        for (int mb = 0; mb < TM; ++mb) {
-          if (EDGE && (nb >= vnb || mb >= vmb)) continue;
-          cr[nb][mb] = P::mma(br[nb], ar[mb], cr[nb][mb]);
-          ci[nb][mb] = P::mma(br[nb], ai[mb], ci[nb][mb]);
+        for (int i = 0; i < TN; ++i) {
+          br[i] = s.b[buf][0][kk][wn * TN * 16 + i * 16 + l16];
+          bi[i] = s.b[buf][1][kk][wn * TN * 16 + i * 16 + l16];
         }
 #pragma unroll
-      for (int nb = 0; nb < TN; ++nb)
-#pragma unroll
-        for (int mb = 0; mb < TM; ++mb) {
-          if (EDGE && (nb >= vnb || mb >= vmb)) continue;
-          cr[nb][mb] = P::mma(-bi[nb], ai[mb], cr[nb][mb]);
-          ci[nb][mb] = P::mma(bi[nb], ar[mb], ci[nb][mb]);
+        for (int i = 0; i < TM; ++i) {
+          ar[i] = s.a[buf][0][kk][wm * TM * 16 + i * 16 + l16];
+          ai[i] = s.a[buf][1][kk][wm * TM * 16 + i * 16 + l16];
         }
+#pragma unroll
+        for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+          for (int mb = 0; mb < TM; ++mb) {
+            cr[nb][mb] = P::mma(br[nb], ar[mb], cr[nb][mb]);
+            ci[nb][mb] = P::mma(br[nb], ai[mb], ci[nb][mb]);
+          }
+#pragma unroll
+        for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+          for (int mb = 0; mb < TM; ++mb) {
+            cr[nb][mb] = P::mma(-bi[nb], ai[mb], cr[nb][mb]);
+            ci[nb][mb] = P::mma(bi[nb], ar[mb], ci[nb][mb]);
+          }
+      }
     }
     if (kt + 1 < nkt) {
       sstore(buf ^ 1);
@@ -256,43 +247,20 @@ __device__ __forceinline__ void zbig_tile(const GemmArgs& g, int64_t tm, int64_t
     zbig_tile_impl<P, WGM, WGN, TM, TN, BK, true>(g, tm, tn, kbeg, kend, part, s);
 }
 
-// Whole launch: tiles [0, tail.full) one per workgroup (XCD-major), then
-// the remaining tiles of the last, partial round split along K into
-// tail.ksplit segments.  A segment stores its partial accumulator and
-// counts itself in; the last segment of a tile to arrive sums the partials
-// in segment order (deterministic), applies the epilogue and resets the
-// counter for the next launch.  No workgroup ever waits on another.
+// A segment has stored its partial product: count it in.  The last segment
+// of a tile to arrive sums the partials in segment order (deterministic),
+// applies the epilogue and resets the tile's counter for the next launch.
 template <class P, int WGM, int WGN, int TM, int TN, int BK>
-__device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& tail) {
+__device__ __forceinline__ void zbig_arrive(const GemmArgs& g, const TailSplit& tail, const WorkItem& w,
+                                            int64_t tiles_n, int* last) {
   using C = Cfg<WGM, WGN, TM, TN, BK>;
   using zv = typename P::cplx;
   using real = typename P::real;
   constexpr int BM = C::BM, BN = C::BN;
-  __shared__ Smem<P, C, BK> s;
-  __shared__ int last;
-  const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const int64_t grid_main = 8 * ((tail.full + 7) / 8);
-  if ((int64_t)blockIdx.x < grid_main) {
-    int64_t tm, tn;
-    if (!map_tile(tail.full, tiles_n, tm, tn)) return;
-    zbig_tile<P, WGM, WGN, TM, TN, BK>(g, tm, tn, s);
-    return;
-  }
-  const int64_t j = (int64_t)blockIdx.x - grid_main;       // tail segment
-  const int64_t tl = j / tail.ksplit, sp = j % tail.ksplit;  // tail tile, split
-  const int64_t tile = tail.full + tl;
-  const int64_t tm = tile / tiles_n, tn = tile % tiles_n;
-  const int64_t nkt = (g.K + BK - 1) / BK;
-  const int64_t per = (nkt + tail.ksplit - 1) / tail.ksplit;
-  const int64_t kbeg = sp * per * BK;
-  const int64_t kend = (sp + 1) * per * BK < g.K ? (sp + 1) * per * BK : g.K;
-  zv* part = reinterpret_cast<zv*>(tail.ws) + j * (int64_t)(BM * BN);
-  zbig_tile<P, WGM, WGN, TM, TN, BK>(g, tm, tn, s, kbeg, kend, part);
+  const int64_t tl = w.seg / tail.ksplit;
+  const int64_t tm = w.tile / tiles_n, tn = w.tile % tiles_n;
   __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(tail.counters + tl, 1) == tail.ksplit - 1);
-  __syncthreads();
-  if (!last) return;
+  if (wg_fetch_add(tail.counters + tl, 1, last) != tail.ksplit - 1) return;
   __threadfence();
   const zv* parts = reinterpret_cast<const zv*>(tail.ws) + tl * tail.ksplit * (int64_t)(BM * BN);
   zv* Y = reinterpret_cast<zv*>(g.Y);
@@ -322,6 +290,26 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& ta
     Y[m + n * g.ldy] = out;
   }
   if (threadIdx.x == 0) tail.counters[tl] = 0;
+}
+
+// Whole launch: a persistent grid takes whole tiles and tail segments from
+// the per-XCD work queue (sched.hpp) until its XCD's share is done.
+template <class P, int WGM, int WGN, int TM, int TN, int BK>
+__device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& tail) {
+  using C = Cfg<WGM, WGN, TM, TN, BK>;
+  using zv = typename P::cplx;
+  constexpr int BM = C::BM, BN = C::BN;
+  __shared__ Smem<P, C, BK> s;
+  __shared__ int last, item;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const QueueShare q = queue_share(tail, ((g.M + BM - 1) / BM) * tiles_n);
+  for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
+    const WorkItem w = work_item(tail, i, g.K, BK);
+    zv* part = w.seg < 0 ? nullptr : reinterpret_cast<zv*>(tail.ws) + w.seg * (int64_t)(BM * BN);
+    zbig_tile<P, WGM, WGN, TM, TN, BK>(g, w.tile / tiles_n, w.tile % tiles_n, s, w.kbeg, w.kend, part);
+    if (w.seg >= 0) zbig_arrive<P, WGM, WGN, TM, TN, BK>(g, tail, w, tiles_n, &last);
+  }
+  queue_leave(tail);
 }
 
 // Grouped, persistent form for many problems at once: row `step` of the
@@ -388,9 +376,10 @@ __global__ void counters_zero(int* c, int n) {
 }
 
 struct CfgInfo {
-  int bm, bn, bk, nt, wg_per_cu;
+  int bm, bn, bk, nt, wg_per_cu, wgm, wgn;
 };
-constexpr CfgInfo kCfg[2] = {{C0::BM, C0::BN, C0::BK_, C0::NT, 1}, {C1::BM, C1::BN, C1::BK_, C1::NT, 2}};
+constexpr CfgInfo kCfg[2] = {{C0::BM, C0::BN, C0::BK_, C0::NT, 1, C0::WGM_, C0::WGN_},
+                             {C1::BM, C1::BN, C1::BK_, C1::NT, 2, C1::WGM_, C1::WGN_}};
 
 }  // namespace
 
@@ -427,8 +416,8 @@ int grouped_grid(int cfg) { return (int)(8 * cdiv((int64_t)cu_count() * kCfg[cfg
 int64_t tail_workspace_bytes() { return (int64_t)kTailMaxSegments * C0::BM * C0::BN * 16; }
 
 int tail_counters_init(int* counters, hipStream_t s) {
-  hipLaunchKernelGGL(counters_zero, dim3((kTailMaxSegments + 255) / 256), dim3(256), 0, s, counters,
-                     kTailMaxSegments);
+  hipLaunchKernelGGL(counters_zero, dim3((kTailCounterInts + 255) / 256), dim3(256), 0, s, counters,
+                     kTailCounterInts);
   CHASE_CHK_LAUNCH();
   return kOk;
 }
@@ -437,37 +426,14 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
                         int choice) {
   if (g.M <= 0 || g.N <= 0) return kOk;
   if (g.ws != nullptr || g.upper_b || g.lower_only || g.bscale != nullptr) return -1;
+  if (!tail_ws || !tail_counters) return -1;
   const int cfg = (choice == kChoiceT1Tail && filter_symbol) ? 1 : 0;
   const CfgInfo& c = kCfg[cfg];
-  const int64_t tiles = cdiv(g.M, c.bm) * cdiv(g.N, c.bn);
-  const int64_t G = (int64_t)cu_count() * c.wg_per_cu;  // concurrently resident workgroups
+  TileGeom geo;
+  geo.M = g.M; geo.N = g.N; geo.bm = c.bm; geo.bn = c.bn; geo.wgm = c.wgm; geo.wgn = c.wgn;
   TailSplit t;
-  t.full = tiles;
-  t.ksplit = 1;
-  t.ws = tail_ws;
-  t.counters = tail_counters;
-  const int64_t nkt = cdiv(g.K, c.bk);
-  const int64_t rem = tiles % G;
-  const bool use_tail = tail_ws && tail_counters && rem > 0 && choice != kChoiceT0NoTail;
-  if (use_tail) {
-    // split the last round's tiles along K to fill the idle CUs: minimise
-    // ceil(rem * s / G) / s (in units of one tile's time)
-    int best = 1;
-    double cost_best = 1.0;
-    for (int sp = 2; sp <= 8; ++sp) {
-      if (nkt < 16 * sp || rem * sp > kTailMaxSegments) break;
-      const double cost = (double)cdiv(rem * sp, G) / sp;
-      if (cost < cost_best - 1e-9) {
-        cost_best = cost;
-        best = sp;
-      }
-    }
-    if (best > 1) {
-      t.full = tiles - rem;
-      t.ksplit = best;
-    }
-  }
-  const int64_t grid = 8 * cdiv(t.full, 8) + (tiles - t.full) * t.ksplit;
+  const int64_t grid = plan_schedule(geo, cdiv(g.K, c.bk), (int64_t)cu_count() * c.wg_per_cu, 16,
+                                     choice != kChoiceT0NoTail, tail_ws, tail_counters, &t);
   GemmArgs a = g;
   if (a.K <= 0) a.alpha = 0.0;
   if (!filter_symbol)
@@ -482,6 +448,7 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
 
 int cfilter_big_launch(const CGemmArgs& c, hipStream_t s, void* tail_ws, int* tail_counters) {
   if (c.M <= 0 || c.N <= 0) return kOk;
+  if (!tail_ws || !tail_counters) return -1;
   // The kernel reads operands through the same argument block as the FP64
   // one; pointers are reinterpreted as complex64 inside.
   GemmArgs g;
@@ -492,31 +459,10 @@ int cfilter_big_launch(const CGemmArgs& c, hipStream_t s, void* tail_ws, int* ta
   g.Z = reinterpret_cast<const z64*>(c.Z); g.ldz = c.ldz;
   g.alpha = c.alpha; g.beta = c.beta; g.gamma = c.gamma;
   if (g.K <= 0) g.alpha = 0.0;
-  const int64_t tiles = cdiv(g.M, CF::BM) * cdiv(g.N, CF::BN);
-  const int64_t G = cu_count();
+  TileGeom geo;
+  geo.M = g.M; geo.N = g.N; geo.bm = CF::BM; geo.bn = CF::BN; geo.wgm = CF::WGM_; geo.wgn = CF::WGN_;
   TailSplit t;
-  t.full = tiles;
-  t.ws = tail_ws;
-  t.counters = tail_counters;
-  const int64_t nkt = cdiv(g.K, CF::BK_);
-  const int64_t rem = tiles % G;
-  if (tail_ws && tail_counters && rem > 0) {
-    int best = 1;
-    double cost_best = 1.0;
-    for (int sp = 2; sp <= 8; ++sp) {
-      if (nkt < 16 * sp || rem * sp > kTailMaxSegments) break;
-      const double cost = (double)cdiv(rem * sp, G) / sp;
-      if (cost < cost_best - 1e-9) {
-        cost_best = cost;
-        best = sp;
-      }
-    }
-    if (best > 1) {
-      t.full = tiles - rem;
-      t.ksplit = best;
-    }
-  }
-  const int64_t grid = 8 * cdiv(t.full, 8) + (tiles - t.full) * t.ksplit;
+  const int64_t grid = plan_schedule(geo, cdiv(g.K, CF::BK_), cu_count(), 16, true, tail_ws, tail_counters, &t);
   hipLaunchKernelGGL(cfilter_step, dim3((unsigned)grid), dim3(CF::NT), 0, s, g, t);
   CHASE_CHK_LAUNCH();
   return kOk;

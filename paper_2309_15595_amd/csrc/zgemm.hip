@@ -266,7 +266,7 @@ __global__ void zsplitk_reduce(const zv* ws, int64_t stride, int splits, int64_t
 
 }  // namespace
 
-int zgemm_launch(int opa, int opb, const GemmArgs& g_in, hipStream_t stream, bool filter_symbol) {
+int zgemm_launch(int opa, int opb, const GemmArgs& g_in, hipStream_t stream) {
   GemmArgs g = g_in;
   if (g.M <= 0 || g.N <= 0) return kOk;
   const int64_t tiles = cdiv(g.M, BM) * cdiv(g.N, BN);
@@ -276,9 +276,7 @@ int zgemm_launch(int opa, int opb, const GemmArgs& g_in, hipStream_t stream, boo
     g.alpha = 0.0;
   }
   g.ws = nullptr;
-  if (filter_symbol) {
-    return zgemm_nn_big_launch(g, stream, true);
-  } else if (opa == 0 && opb == 0) {
+  if (opa == 0 && opb == 0) {
     hipLaunchKernelGGL(zgemm_nn, blocks, dim3(NT), 0, stream, g);
   } else if (opa == 1 && opb == 0) {
     hipLaunchKernelGGL(zgemm_cn, blocks, dim3(NT), 0, stream, g);
