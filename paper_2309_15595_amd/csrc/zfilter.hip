@@ -312,6 +312,198 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& ta
   queue_leave(tail);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 step with direct-to-LDS operand loads.
+//
+// global_load_lds_dwordx4 moves each lane's 16 bytes (one complex128) from
+// any global address straight to LDS at base + 16 * lane, so the operands
+// need no staging registers and the loads leave the waves' instruction
+// stream almost empty; the freed registers buy a K-tile of 16 (half the
+// barriers of the staged schedule) with two LDS stages of 64 KB.
+//   H: [k][m], 2 KB per k row; one instruction moves 64 consecutive rows of
+//      one column of H (coalesced), a fragment read (16 lanes, consecutive
+//      m, one k) is one 256-byte run.
+//   X: [n][k ^ (n & 15)], 256 B per column; one instruction moves 16 k of
+//      each of 4 columns (coalesced, permuted inside the 256-byte run), and
+//      the XOR makes the 16 lanes of a fragment read (consecutive n, one k)
+//      hit 16 different 16-byte bank groups.
+// Complex values stay interleaved: one 16-byte LDS read yields both the
+// real and the imaginary operand of a lane.  Rows of H beyond M and columns
+// of X beyond N are not loaded (they only reach discarded outputs); k beyond
+// the K range is written as zero.
+// ---------------------------------------------------------------------------
+namespace dz {
+constexpr int BM = 128, BN = 128, BK = 16, NT = 512;
+constexpr int WGM = 2, WGN = 4, TM = 4, TN = 2;
+constexpr int A_BYTES = BK * BM * 16;
+constexpr int B_BYTES = BN * BK * 16;
+constexpr int STAGE = A_BYTES + B_BYTES;
+}  // namespace dz
+
+// Loads of K-tile [k0, k0 + 16) of tile (m0, n0) into `stage`: 64
+// instructions, 8 per wave.
+template <bool EDGE>
+__device__ __forceinline__ void dz_issue(const GemmArgs& g, int64_t m0, int64_t n0, int64_t k0, int64_t kend,
+                                         unsigned char* stage, int wave, int lane) {
+  using namespace dz;
+  const zv* A = reinterpret_cast<const zv*>(g.A);
+  const zv* B = reinterpret_cast<const zv*>(g.B);
+  const bool kfull = k0 + BK <= kend;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ia = wave * 4 + r;  // k row ia / 2, rows 64 * (ia % 2) ..
+    const int kr = ia >> 1, half = ia & 1;
+    const int64_t k = k0 + kr;
+    unsigned char* dst = stage + kr * (BM * 16) + half * 1024;
+    const int64_t m = m0 + half * 64 + lane;
+    if (kfull || k < kend) {
+      if (!EDGE || m < g.M) __builtin_amdgcn_global_load_lds(A + m + k * g.lda, dst, 16, 0, 0);
+    } else {
+      reinterpret_cast<zv*>(dst)[lane] = zv{0.0, 0.0};
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ib = wave * 4 + r;  // columns 4 ib .. 4 ib + 3
+    const int nl = ib * 4 + (lane >> 4);
+    const int kl = (lane & 15) ^ (nl & 15);
+    const int64_t n = n0 + nl, k = k0 + kl;
+    unsigned char* dst = stage + A_BYTES + ib * 1024;
+    if (kfull || k < kend) {
+      if (!EDGE || n < g.N) __builtin_amdgcn_global_load_lds(B + k + n * g.ldb, dst, 16, 0, 0);
+    } else {
+      reinterpret_cast<zv*>(dst)[lane] = zv{0.0, 0.0};
+    }
+  }
+}
+
+template <bool EDGE>
+__device__ __forceinline__ void zdma_tile_impl(const GemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg, int64_t kend,
+                                               zv* part, unsigned char* lds) {
+  using namespace dz;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const bool active = !EDGE || (m0 + wm * TM * 16 < g.M && n0 + wn * TN * 16 < g.N);
+  const int issue_at = wave < 4 ? 0 : 2;
+  f64x4 cr[TN][TM], ci[TN][TM];
+#pragma unroll
+  for (int a = 0; a < TN; ++a)
+#pragma unroll
+    for (int b = 0; b < TM; ++b) {
+      cr[a][b] = f64x4{0, 0, 0, 0};
+      ci[a][b] = f64x4{0, 0, 0, 0};
+    }
+  const int64_t nkt = (kend - kbeg + BK - 1) / BK;
+  if (nkt > 0) dz_issue<EDGE>(g, m0, n0, kbeg, kend, lds, wave, lane);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const unsigned char* cur = lds + (kt & 1) * STAGE;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      // waves w and w + 4 share a SIMD: the first issues its loads before
+      // K-substep 0, the second before substep 2, so one wave's load issue
+      // always overlaps the other's MFMAs
+      if (ks == issue_at && kt + 1 < nkt)
+        dz_issue<EDGE>(g, m0, n0, kbeg + (kt + 1) * BK, kend, lds + ((kt + 1) & 1) * STAGE, wave, lane);
+      if (!active) continue;
+      const int kk = ks * 4 + kq;
+      double br[TN], bi[TN], ar[TM], ai[TM];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = wn * TN * 16 + j * 16 + l16;
+        const zv v = *reinterpret_cast<const zv*>(cur + A_BYTES + n * (BK * 16) + ((kk ^ (n & 15)) << 4));
+        br[j] = v.re;
+        bi[j] = v.im;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int m = wm * TM * 16 + i * 16 + l16;
+        const zv v = *reinterpret_cast<const zv*>(cur + kk * (BM * 16) + (m << 4));
+        ar[i] = v.re;
+        ai[i] = v.im;
+      }
+#pragma unroll
+      for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < TM; ++mb) {
+          cr[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[nb], ar[mb], cr[nb][mb], 0, 0, 0);
+          ci[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[nb], ai[mb], ci[nb][mb], 0, 0, 0);
+        }
+#pragma unroll
+      for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < TM; ++mb) {
+          cr[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi[nb], ai[mb], cr[nb][mb], 0, 0, 0);
+          ci[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[nb], ar[mb], ci[nb][mb], 0, 0, 0);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next K-tile have landed
+    __syncthreads();
+  }
+
+  if (part != nullptr) {
+#pragma unroll
+    for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+      for (int mb = 0; mb < TM; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int nl = wn * TN * 16 + nb * 16 + PF64::row(kq, r);
+          const int ml = wm * TM * 16 + mb * 16 + l16;
+          part[ml + nl * BM] = zv{cr[nb][mb][r], ci[nb][mb][r]};
+        }
+    return;
+  }
+  zv* Y = reinterpret_cast<zv*>(g.Y);
+  const zv* Z = reinterpret_cast<const zv*>(g.Z);
+#pragma unroll
+  for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+    for (int mb = 0; mb < TM; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t n = n0 + wn * TN * 16 + nb * 16 + PF64::row(kq, r);
+        const int64_t m = m0 + wm * TM * 16 + mb * 16 + l16;
+        if (m >= g.M || n >= g.N) continue;
+        zv out{g.alpha * cr[nb][mb][r], g.alpha * ci[nb][mb][r]};
+        if (g.beta != 0.0) {
+          const zv y = Y[m + n * g.ldy];
+          out.re += g.beta * y.re;
+          out.im += g.beta * y.im;
+        }
+        if (g.gamma != 0.0) {
+          const zv z = Z[m + n * g.ldz];
+          out.re += g.gamma * z.re;
+          out.im += g.gamma * z.im;
+        }
+        Y[m + n * g.ldy] = out;
+      }
+}
+
+// Whole launch of the direct-to-LDS step on the per-XCD work queue.
+__device__ __forceinline__ void zdma_body(const GemmArgs& g, const TailSplit& tail) {
+  using namespace dz;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+  __shared__ int last, item;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const QueueShare q = queue_share(tail, ((g.M + BM - 1) / BM) * tiles_n);
+  for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
+    const WorkItem w = work_item(tail, i, g.K, BK);
+    zv* part = w.seg < 0 ? nullptr : reinterpret_cast<zv*>(tail.ws) + w.seg * (int64_t)(BM * BN);
+    const int64_t tm = w.tile / tiles_n, tn = w.tile % tiles_n;
+    if ((tm + 1) * BM <= g.M && (tn + 1) * BN <= g.N)
+      zdma_tile_impl<false>(g, tm, tn, w.kbeg, w.kend, part, lds);
+    else
+      zdma_tile_impl<true>(g, tm, tn, w.kbeg, w.kend, part, lds);
+    if (w.seg >= 0) zbig_arrive<PF64, WGM, WGN, TM, TN, BK>(g, tail, w, tiles_n, &last);
+  }
+  queue_leave(tail);
+}
+
 // Grouped, persistent form for many problems at once: row `step` of the
 // descriptor table lists one GEMM per problem with its tile count as a running
 // prefix sum.  A fixed grid (a multiple of 8 workgroups) walks the tiles
@@ -351,12 +543,12 @@ __device__ __forceinline__ void zbig_grouped(const GroupEntry* __restrict__ tabl
 using C0 = Cfg<T0_ARGS>;
 using C1 = Cfg<T1_ARGS>;
 
-__global__ __launch_bounds__(C0::NT, 1) void zfilter_step(GemmArgs g, TailSplit t) { zbig_body<PF64, T0_ARGS>(g, t); }
+__global__ __launch_bounds__(dz::NT, 1) void zfilter_step(GemmArgs g, TailSplit t) { zdma_body(g, t); }
 __global__ __launch_bounds__(C1::NT, 2) void zfilter_step_n64(GemmArgs g, TailSplit t) {
   zbig_body<PF64, T1_ARGS>(g, t);
 }
 // Same schedule for the other large H-times-block products (Rayleigh-Ritz H C).
-__global__ __launch_bounds__(C0::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit t) { zbig_body<PF64, T0_ARGS>(g, t); }
+__global__ __launch_bounds__(dz::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit t) { zdma_body(g, t); }
 // FP32 filter step of the mixed-precision solve (complex64 H and X, FP32
 // accumulation): 128 x 128 tile, 8 waves of 64 x 32, K tile 16.
 #define TF32_ARGS 2, 4, 4, 2, 16
@@ -380,6 +572,8 @@ struct CfgInfo {
 };
 constexpr CfgInfo kCfg[2] = {{C0::BM, C0::BN, C0::BK_, C0::NT, 1, C0::WGM_, C0::WGN_},
                              {C1::BM, C1::BN, C1::BK_, C1::NT, 2, C1::WGM_, C1::WGN_}};
+// the direct-to-LDS FP64 step (zfilter_step, zgemm_nn_big)
+constexpr CfgInfo kDma = {dz::BM, dz::BN, dz::BK, dz::NT, 1, dz::WGM, dz::WGN};
 
 }  // namespace
 
@@ -428,7 +622,7 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
   if (g.ws != nullptr || g.upper_b || g.lower_only || g.bscale != nullptr) return -1;
   if (!tail_ws || !tail_counters) return -1;
   const int cfg = (choice == kChoiceT1Tail && filter_symbol) ? 1 : 0;
-  const CfgInfo& c = kCfg[cfg];
+  const CfgInfo& c = cfg == 1 ? kCfg[1] : kDma;
   TileGeom geo;
   geo.M = g.M; geo.N = g.N; geo.bm = c.bm; geo.bn = c.bn; geo.wgm = c.wgm; geo.wgn = c.wgn;
   TailSplit t;
@@ -437,11 +631,11 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
   GemmArgs a = g;
   if (a.K <= 0) a.alpha = 0.0;
   if (!filter_symbol)
-    hipLaunchKernelGGL(zgemm_nn_big, dim3((unsigned)grid), dim3(C0::NT), 0, s, a, t);
+    hipLaunchKernelGGL(zgemm_nn_big, dim3((unsigned)grid), dim3(dz::NT), 0, s, a, t);
   else if (cfg == 1)
     hipLaunchKernelGGL(zfilter_step_n64, dim3((unsigned)grid), dim3(C1::NT), 0, s, a, t);
   else
-    hipLaunchKernelGGL(zfilter_step, dim3((unsigned)grid), dim3(C0::NT), 0, s, a, t);
+    hipLaunchKernelGGL(zfilter_step, dim3((unsigned)grid), dim3(dz::NT), 0, s, a, t);
   CHASE_CHK_LAUNCH();
   return kOk;
 }
