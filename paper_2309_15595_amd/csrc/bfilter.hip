@@ -128,21 +128,33 @@ __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn
     if (nkt > 1) gload(kbeg + BK);
   }
   __syncthreads();
+  // Row block at which the wave stores the next K-tile and loads the one
+  // after: waves w and w + 4 share a SIMD; staggering them keeps one wave's
+  // store / load issue under the other's MFMAs.
+  const int stage_at = wave >= 4 ? TM / 2 : 0;
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int buf = (int)(kt & 1);
-    if (active) {
+    {
       bf16x8 xf[TN][4];
+      if (active) {
 #pragma unroll
-      for (int nb = 0; nb < TN; ++nb) {
-        const int n = wn * 32 + nb * 16 + l16;
+        for (int nb = 0; nb < TN; ++nb) {
+          const int n = wn * 32 + nb * 16 + l16;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const uint4 w = s.x[buf][p][n][swz(n, kq)];
-          xf[nb][p] = __builtin_bit_cast(bf16x8, w);
+          for (int p = 0; p < 4; ++p) {
+            const uint4 w = s.x[buf][p][n][swz(n, kq)];
+            xf[nb][p] = __builtin_bit_cast(bf16x8, w);
+          }
         }
       }
 #pragma unroll
       for (int mb = 0; mb < TM; ++mb) {
+        // buffer buf ^ 1 was last read before the previous barrier
+        if (mb == stage_at && kt + 1 < nkt) {
+          sstore(buf ^ 1);
+          if (kt + 2 < nkt) gload(kbeg + (kt + 2) * BK);
+        }
+        if (!active) continue;
         const int m = wm * 64 + mb * 16 + l16;
         bf16x8 hf[4];
 #pragma unroll
@@ -156,10 +168,6 @@ __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn
         BMMA(rp, 1, 0) BMMA(rn_, 3, 2) BMMA(im, 1, 2) BMMA(im, 3, 0)
 #undef BMMA
       }
-    }
-    if (kt + 1 < nkt) {
-      sstore(buf ^ 1);
-      if (kt + 2 < nkt) gload(kbeg + (kt + 2) * BK);
     }
     __syncthreads();
   }

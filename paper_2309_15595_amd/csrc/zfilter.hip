@@ -106,6 +106,11 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
   const int l16 = lane & 15, kq = lane >> 4;
   // does this wave's sub-tile touch the output? (wave-uniform)
   const bool active = !EDGE || (m0 + wm * TM * 16 < g.M && n0 + wn * TN * 16 < g.N);
+  // K-substep at which the wave stores the next K-tile to LDS and loads the
+  // one after: waves w and w + 4 of an 8-wave workgroup share a SIMD, and
+  // staggering them keeps one wave's store / load issue under the other's
+  // MFMAs instead of both stalling the matrix pipe after each barrier
+  const int stage_at = (WGM * WGN == 8 && wave >= 4) ? BK / 8 : 0;
 
   accv cr[TN][TM], ci[TN][TM];
 #pragma unroll
@@ -157,40 +162,40 @@ __device__ __forceinline__ void zbig_tile_impl(const GemmArgs& g, int64_t tm, in
   __syncthreads();
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int buf = (int)(kt & 1);
-    if (active) {
 #pragma unroll
-      for (int ks = 0; ks < BK / 4; ++ks) {
-        const int kk = ks * 4 + kq;
-        real br[TN], bi[TN], ar[TM], ai[TM];
-#pragma unroll
-        for (int i = 0; i < TN; ++i) {
-          br[i] = s.b[buf][0][kk][wn * TN * 16 + i * 16 + l16];
-          bi[i] = s.b[buf][1][kk][wn * TN * 16 + i * 16 + l16];
-        }
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          ar[i] = s.a[buf][0][kk][wm * TM * 16 + i * 16 + l16];
-          ai[i] = s.a[buf][1][kk][wm * TM * 16 + i * 16 + l16];
-        }
-#pragma unroll
-        for (int nb = 0; nb < TN; ++nb)
-#pragma unroll
-          for (int mb = 0; mb < TM; ++mb) {
-            cr[nb][mb] = P::mma(br[nb], ar[mb], cr[nb][mb]);
-            ci[nb][mb] = P::mma(br[nb], ai[mb], ci[nb][mb]);
-          }
-#pragma unroll
-        for (int nb = 0; nb < TN; ++nb)
-#pragma unroll
-          for (int mb = 0; mb < TM; ++mb) {
-            cr[nb][mb] = P::mma(-bi[nb], ai[mb], cr[nb][mb]);
-            ci[nb][mb] = P::mma(bi[nb], ar[mb], ci[nb][mb]);
-          }
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      // buffer buf ^ 1 was last read before the previous barrier
+      if (ks == stage_at && kt + 1 < nkt) {
+        sstore(buf ^ 1);
+        if (kt + 2 < nkt) gload(kbeg + (kt + 2) * BK);
       }
-    }
-    if (kt + 1 < nkt) {
-      sstore(buf ^ 1);
-      if (kt + 2 < nkt) gload(kbeg + (kt + 2) * BK);
+      if (!active) continue;
+      const int kk = ks * 4 + kq;
+      real br[TN], bi[TN], ar[TM], ai[TM];
+#pragma unroll
+      for (int i = 0; i < TN; ++i) {
+        br[i] = s.b[buf][0][kk][wn * TN * 16 + i * 16 + l16];
+        bi[i] = s.b[buf][1][kk][wn * TN * 16 + i * 16 + l16];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        ar[i] = s.a[buf][0][kk][wm * TM * 16 + i * 16 + l16];
+        ai[i] = s.a[buf][1][kk][wm * TM * 16 + i * 16 + l16];
+      }
+#pragma unroll
+      for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < TM; ++mb) {
+          cr[nb][mb] = P::mma(br[nb], ar[mb], cr[nb][mb]);
+          ci[nb][mb] = P::mma(br[nb], ai[mb], ci[nb][mb]);
+        }
+#pragma unroll
+      for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < TM; ++mb) {
+          cr[nb][mb] = P::mma(-bi[nb], ai[mb], cr[nb][mb]);
+          ci[nb][mb] = P::mma(bi[nb], ar[mb], ci[nb][mb]);
+        }
     }
     __syncthreads();
   }
