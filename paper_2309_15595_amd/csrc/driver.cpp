@@ -490,8 +490,9 @@ static int gram(Workspace& w, const z64* X, int64_t ldx, int64_t n, hipStream_t 
   g.A = X; g.lda = ldx;
   g.B = X; g.ldb = ldx;
   g.Y = w.G; g.ldy = n;
-  const int splits = choose_splits(n, n, w.N, w.max_splits);
-  return zgemm_splitk(1, 0, g, w.ws, splits, 1, s);
+  // lower triangle only: the Cholesky factorisation and the shift read nothing else
+  const int splits = choose_splits(n, n, w.N, w.max_splits, true);
+  return zgemm_splitk(1, 0, g, w.ws, splits, 2, s);
 }
 
 // X <- X R^{-1} with R = L^H from G = L L^H.  Returns 1 in *failed when the
@@ -605,12 +606,12 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   g.Y = w.B; g.ldy = N;
   int st = zgemm_nn_big_launch(g, s, false, w.tail_ws, w.tail_counters);
   if (st) return st;
-  GemmArgs q;  // G = Q^H B, Hermitised
+  GemmArgs q;  // G = Q^H B, lower triangle (the eigensolver reads nothing else)
   q.M = n; q.N = n; q.K = N;
   q.A = Q; q.lda = ldq;
   q.B = w.B; q.ldb = N;
   q.Y = w.G; q.ldy = n;
-  st = zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits), 1, s);
+  st = zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits, true), 2, s);
   if (st) return st;
   rocblas_set_stream(w.rb, s);
   rocblas_status r = rocsolver_zheevd(w.rb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n,

@@ -83,11 +83,13 @@ int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int gri
 // Grid filling every CU with resident workgroups of configuration cfg.
 int grouped_grid(int cfg);
 // Split over K into `splits` partial products in `ws`, summed in fixed order;
-// hermitise = 1 stores (S + S^H)/2 (M == N).
+// hermitise = 1 stores (S + S^H)/2 (M == N); hermitise = 2 computes and
+// stores only the lower triangle of a Hermitian product (M == N), with a real
+// diagonal, leaving the strict upper triangle of Y untouched.
 int zgemm_splitk(int opa, int opb, const GemmArgs& g, void* ws, int splits, int hermitise,
                  hipStream_t s);
 int64_t zgemm_splitk_workspace(int64_t M, int64_t N, int splits);
-int choose_splits(int64_t M, int64_t N, int64_t K, int max_splits);
+int choose_splits(int64_t M, int64_t N, int64_t K, int max_splits, bool lower = false);
 
 // Complex FP32 GEMM (mixed-precision filter): same contract with complex64 data.
 struct CGemmArgs {

@@ -239,13 +239,15 @@ __global__ void zsplitk_reduce(const zv* ws, int64_t stride, int splits, int64_t
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   int64_t m = idx % M, n = idx / M;
+  if (hermitise == 2 && m < n) return;  // lower triangle only
   double sr = 0.0, si = 0.0;
   for (int s = 0; s < splits; ++s) {
     zv v = ws[s * stride + m + n * M];
     sr += v.re;
     si += v.im;
   }
-  if (hermitise) {  // (S + S^H) / 2, M == N
+  if (hermitise == 2 && m == n) si = 0.0;  // real diagonal
+  if (hermitise == 1) {  // (S + S^H) / 2, M == N
     double tr = 0.0, ti = 0.0;
     for (int s = 0; s < splits; ++s) {
       zv v = ws[s * stride + n + m * M];
@@ -293,8 +295,12 @@ int64_t zgemm_splitk_workspace(int64_t M, int64_t N, int splits) {
   return (int64_t)splits * M * N;  // complex entries
 }
 
-int choose_splits(int64_t M, int64_t N, int64_t K, int max_splits) {
-  const int64_t tiles = cdiv(M, BM) * cdiv(N, BN);
+int choose_splits(int64_t M, int64_t N, int64_t K, int max_splits, bool lower) {
+  int64_t tiles = cdiv(M, BM) * cdiv(N, BN);
+  if (lower) {  // tiles holding an element on or below the diagonal
+    tiles = 0;
+    for (int64_t n0 = 0; n0 < N; n0 += BN) tiles += cdiv(M - (n0 / BM) * BM, BM);
+  }
   int64_t want = cdiv(1024, tiles);                 // aim at ~1024 workgroups
   int64_t cap = K / (4 * BK) > 1 ? K / (4 * BK) : 1; // at least 4 K-steps per split
   int64_t s = want < cap ? want : cap;
@@ -314,6 +320,7 @@ int zgemm_splitk(int opa, int opb, const GemmArgs& g_in, void* ws, int splits, i
   g.ws = reinterpret_cast<z64*>(ws);
   g.ws_stride = g.M * g.N;
   g.k_chunk = kchunk;
+  if (hermitise == 2) g.lower_only = 1;  // tiles wholly above the diagonal are never read
   const int64_t tiles = cdiv(g.M, BM) * cdiv(g.N, BN);
   dim3 blocks((unsigned)(8 * cdiv(tiles, 8)), (unsigned)splits, 1);
   if (opa == 1 && opb == 0) {
