@@ -221,10 +221,9 @@ __device__ __forceinline__ void btile_any(const BGemmArgs& g, int64_t tm, int64_
 
 // A segment has stored its partial tile: count it in; the last segment of a
 // tile to arrive sums the partials in segment order and applies the epilogue.
-__device__ __forceinline__ void barrive(const BGemmArgs& g, const TailSplit& tail, const WorkItem& w,
-                                        int64_t tiles_n, int* last) {
+__device__ __forceinline__ void barrive(const BGemmArgs& g, const TailSplit& tail, const WorkItem& w, int* last) {
   const int64_t tl = w.seg / tail.ksplit;
-  const int64_t tm = w.tile / tiles_n, tn = w.tile % tiles_n;
+  const int64_t tm = w.tm, tn = w.tn;
   __threadfence();
   if (wg_fetch_add(tail.counters + tl, 1, last) != tail.ksplit - 1) return;
   __threadfence();
@@ -262,13 +261,13 @@ __global__ __launch_bounds__(NT, 1) void bfilter_step(BGemmArgs g, TailSplit tai
   __shared__ BSmem s;
   __shared__ int last, item;
   const int64_t kpad = (g.K + BK - 1) / BK * BK;
-  const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const QueueShare q = queue_share(tail, ((g.M + BM - 1) / BM) * tiles_n);
+  const TileOrder o = tile_order(g.M, g.N, BM, BN);
+  const QueueShare q = queue_share(tail, o);
   for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
-    const WorkItem w = work_item(tail, i, kpad, BK);
+    const WorkItem w = work_item(tail, o, i, kpad, BK);
     cv* part = w.seg < 0 ? nullptr : reinterpret_cast<cv*>(tail.ws) + w.seg * (int64_t)(BM * BN);
-    btile_any(g, w.tile / tiles_n, w.tile % tiles_n, w.kbeg, w.kend, part, s);
-    if (w.seg >= 0) barrive(g, tail, w, tiles_n, &last);
+    btile_any(g, w.tm, w.tn, w.kbeg, w.kend, part, s);
+    if (w.seg >= 0) barrive(g, tail, w, &last);
   }
   queue_leave(tail);
 }

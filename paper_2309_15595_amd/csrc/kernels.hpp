@@ -42,6 +42,10 @@ struct TailSplit {
 struct TileGeom {
   int64_t M = 0, N = 0;
   int bm = 128, bn = 128, wgm = 2, wgn = 4;
+  // last column tiles with at most narrow_cols live columns are computed by
+  // 8 x 1 waves of (bm / 8) x (bn / wgn), those with at most 2 narrow_cols by
+  // 4 x 2 waves of (bm / 4) x (bn / wgn) (0: neither layout)
+  int narrow_cols = 0;
 };
 // Split and grid of one launch of `nkt` K-tiles per tile with `resident`
 // workgroups resident at once (schedule.cpp).  Candidate splits of the last

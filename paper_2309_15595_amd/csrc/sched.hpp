@@ -23,10 +23,41 @@
 
 namespace chase {
 
+// Order of the tiles of an M x N output in bm x bn tiles.  Row panels of H
+// come one after the other (tiles sharing a panel are neighbours); when the
+// last column of tiles is ragged, its tiles (cheaper: fewer live columns)
+// are all placed after the full-width ones, so the queues hand out the
+// longest items first.  plan_schedule numbers tiles the same way.
+struct TileOrder {
+  int64_t tiles_m, tiles_n;
+  bool edge_last;
+};
+
+__host__ __device__ __forceinline__ TileOrder tile_order(int64_t M, int64_t N, int bm, int bn) {
+  TileOrder o;
+  o.tiles_m = (M + bm - 1) / bm;
+  o.tiles_n = (N + bn - 1) / bn;
+  o.edge_last = o.tiles_n > 1 && N % bn != 0;
+  return o;
+}
+
+__host__ __device__ __forceinline__ void tile_rc(const TileOrder& o, int64_t tile, int64_t* tm, int64_t* tn) {
+  const int64_t wide = o.edge_last ? o.tiles_n - 1 : o.tiles_n;
+  const int64_t head = o.tiles_m * wide;
+  if (tile < head) {
+    *tm = tile / wide;
+    *tn = tile % wide;
+  } else {
+    *tm = tile - head;
+    *tn = o.tiles_n - 1;
+  }
+}
+
 // One item of a launch: a whole tile, or K range [kbeg, kend) of a tile
 // whose partial product goes to segment slot `seg` of the tail workspace.
 struct WorkItem {
-  int64_t tile;
+  int64_t tile;  // index in the tile order
+  int64_t tm, tn;
   int64_t seg;  // -1: whole tile
   int64_t kbeg, kend;
 };
@@ -34,46 +65,76 @@ struct WorkItem {
 // Item i of the launch in global order (whole tiles first, then segments);
 // K ranges are in units of bk-wide K-tiles over kext (K rounded as the
 // kernel's loads expect).
-__device__ __forceinline__ WorkItem work_item(const TailSplit& tail, int64_t i, int64_t kext, int bk) {
+__host__ __device__ __forceinline__ WorkItem work_item(const TailSplit& tail, const TileOrder& o, int64_t i,
+                                                       int64_t kext, int bk) {
   WorkItem w;
   if (i < tail.full) {
     w.tile = i;
     w.seg = -1;
     w.kbeg = 0;
     w.kend = kext;
-    return w;
+  } else {
+    const int64_t j = i - tail.full;
+    const int64_t tl = j / tail.ksplit, sp = j % tail.ksplit;
+    const int64_t nkt = (kext + bk - 1) / bk;
+    const int64_t per = (nkt + tail.ksplit - 1) / tail.ksplit;
+    w.tile = tail.full + tl;
+    w.seg = j;
+    w.kbeg = sp * per * bk;
+    w.kend = (sp + 1) * per * bk < kext ? (sp + 1) * per * bk : kext;
   }
-  const int64_t j = i - tail.full;
-  const int64_t tl = j / tail.ksplit, sp = j % tail.ksplit;
-  const int64_t nkt = (kext + bk - 1) / bk;
-  const int64_t per = (nkt + tail.ksplit - 1) / tail.ksplit;
-  w.tile = tail.full + tl;
-  w.seg = j;
-  w.kbeg = sp * per * bk;
-  w.kend = (sp + 1) * per * bk < kext ? (sp + 1) * per * bk : kext;
+  tile_rc(o, w.tile, &w.tm, &w.tn);
   return w;
 }
 
-// This workgroup's share of the queue: its XCD's whole tiles [m_lo, m_lo +
-// n_main) and segments [t_lo, t_lo + n_items - n_main).
+// This workgroup's share of the queue.  The launch's items fall in four
+// classes, taken in this order: whole full-width tiles, whole tiles of the
+// ragged last column, K segments of full-width tiles, K segments of
+// last-column tiles.  XCD x owns a contiguous eighth of each class
+// (neighbouring tiles share a row panel of H on one L2, and every XCD gets
+// the same mix of long and short items).
+constexpr int kQueueClasses = 4;
 struct QueueShare {
   int xcd;
-  int64_t m_lo, n_main, t_lo, n_items;
+  int64_t base[kQueueClasses], lo[kQueueClasses], cnt[kQueueClasses];
+  int64_t n_items;
 };
 
-__device__ __forceinline__ QueueShare queue_share(const TailSplit& tail, int64_t tiles) {
+__host__ __device__ __forceinline__ QueueShare queue_share_for(const TailSplit& tail, const TileOrder& o, int xcd) {
   QueueShare q;
-  q.xcd = (int)(blockIdx.x % 8);
-  const int64_t per_m = (tail.full + 7) / 8;
-  q.m_lo = q.xcd * per_m < tail.full ? q.xcd * per_m : tail.full;
-  const int64_t m_hi = q.m_lo + per_m < tail.full ? q.m_lo + per_m : tail.full;
-  const int64_t nseg = (tiles - tail.full) * tail.ksplit;
-  const int64_t per_t = (nseg + 7) / 8;
-  q.t_lo = q.xcd * per_t < nseg ? q.xcd * per_t : nseg;
-  const int64_t t_hi = q.t_lo + per_t < nseg ? q.t_lo + per_t : nseg;
-  q.n_main = m_hi - q.m_lo;
-  q.n_items = q.n_main + (t_hi - q.t_lo);
+  q.xcd = xcd;
+  const int64_t tiles = o.tiles_m * o.tiles_n;
+  const int64_t head = o.edge_last ? o.tiles_m * (o.tiles_n - 1) : tiles;  // full-width tiles
+  const int64_t f = tail.full, ks = tail.ksplit;
+  const int64_t whole_wide = f < head ? f : head;
+  const int64_t split_wide = f < head ? head - f : 0;  // split tiles that are full-width
+  const int64_t len[kQueueClasses] = {whole_wide, f - whole_wide, split_wide * ks, (tiles - f - split_wide) * ks};
+  const int64_t base[kQueueClasses] = {0, whole_wide, f, f + split_wide * ks};
+  q.n_items = 0;
+  for (int c = 0; c < kQueueClasses; ++c) {
+    const int64_t per = (len[c] + 7) / 8;
+    const int64_t lo = xcd * per < len[c] ? xcd * per : len[c];
+    const int64_t hi = lo + per < len[c] ? lo + per : len[c];
+    q.base[c] = base[c];
+    q.lo[c] = lo;
+    q.cnt[c] = hi - lo;
+    q.n_items += hi - lo;
+  }
   return q;
+}
+
+__device__ __forceinline__ QueueShare queue_share(const TailSplit& tail, const TileOrder& o) {
+  return queue_share_for(tail, o, (int)(blockIdx.x % 8));
+}
+
+// Global item index of the it-th item of a share (it < n_items): whole tile
+// indices below tail.full, segment indices from tail.full on.
+__host__ __device__ __forceinline__ int64_t share_item(const QueueShare& q, int64_t it) {
+  for (int c = 0; c < kQueueClasses - 1; ++c) {
+    if (it < q.cnt[c]) return q.base[c] + q.lo[c] + it;
+    it -= q.cnt[c];
+  }
+  return q.base[kQueueClasses - 1] + q.lo[kQueueClasses - 1] + it;
 }
 
 // Fetch-and-add of `add` on *counter by the workgroup, without a divergent
@@ -101,7 +162,7 @@ __device__ __forceinline__ int wg_fetch_add(int* counter, int add, int* sh) {
 __device__ __forceinline__ int64_t queue_next(const TailSplit& tail, const QueueShare& q, int* item_sh) {
   const int64_t it = wg_fetch_add(tail.queue + q.xcd, 1, item_sh);
   if (it >= q.n_items) return -1;
-  return it < q.n_main ? q.m_lo + it : tail.full + q.t_lo + (it - q.n_main);
+  return share_item(q, it);
 }
 
 // The workgroup is done with the launch; the last one clears the queue.

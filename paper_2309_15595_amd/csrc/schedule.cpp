@@ -20,48 +20,62 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "sched.hpp"
 
 namespace chase {
 
 namespace {
 
-double tile_cost(const TileGeom& g, int64_t tiles_n, int64_t tile) {
-  const int64_t tm = tile / tiles_n, tn = tile % tiles_n;
+constexpr double kSegmentOverhead = 3e-3;  // partial-tile store and sum, per segment
+constexpr double kTileFixed = 0.13;
+
+double tile_cost(const TileGeom& g, int64_t tile) {
+  int64_t tm, tn;
+  tile_rc(tile_order(g.M, g.N, g.bm, g.bn), tile, &tm, &tn);
   const int64_t rm = std::min<int64_t>(g.bm, g.M - tm * g.bm), rn = std::min<int64_t>(g.bn, g.N - tn * g.bn);
   const int waves = g.wgm * g.wgn;
-  const int sub_m = g.bm / g.wgm, sub_n = g.bn / g.wgn;
+  int wgm = g.wgm;  // edge layouts of a ragged last column
+  if (g.narrow_cols > 0 && rn <= g.narrow_cols) wgm = waves;
+  else if (g.narrow_cols > 0 && rn <= 2 * g.narrow_cols) wgm = waves / 2;
+  const int sub_m = g.bm / wgm, sub_n = g.bn / g.wgn;
+  // work of one wave relative to a wave of the main layout
+  const double work = (double)sub_m / (g.bm / g.wgm);
   int load[4] = {0, 0, 0, 0};
   for (int w = 0; w < waves; ++w)
-    if ((w % g.wgm) * sub_m < rm && (w / g.wgm) * sub_n < rn) ++load[w % 4];
+    if ((w % wgm) * sub_m < rm && (w / wgm) * sub_n < rn) ++load[w % 4];
   const int busiest = *std::max_element(load, load + 4);
   const int full = (waves + 3) / 4;
-  return (double)busiest / full;
+  // a fixed share of a tile's time does not shrink with its MFMA work
+  // (prologue, epilogue, barriers): fitted to step times measured at
+  // N = 20000 with 16 to 1300 columns
+  return kTileFixed + (1.0 - kTileFixed) * busiest * work / full;
 }
 
-constexpr double kSegmentOverhead = 3e-3;  // partial-tile store and sum, per segment
 
 // Makespan of the per-XCD queues for `full` whole tiles and the rest split
-// into ks segments each, with `grid` workgroups.
-double simulate(const TileGeom& g, int64_t tiles_n, int64_t tiles, int64_t full, int64_t ks, int64_t grid,
+// into ks segments each, with `grid` workgroups (the device's queue_share).
+double simulate(const TileGeom& g, int64_t tiles, int64_t full, int64_t ks, int64_t grid,
                 const std::vector<double>& cost) {
-  const int64_t nseg = (tiles - full) * ks;
-  const int64_t per_m = cdiv(full, 8), per_t = cdiv(nseg, 8);
+  const TileOrder o = tile_order(g.M, g.N, g.bm, g.bn);
+  TailSplit t;
+  t.full = full;
+  t.ksplit = ks;
   const int64_t wgs = std::max<int64_t>(1, grid / 8);
   double makespan = 0.0;
   for (int x = 0; x < 8; ++x) {
+    const QueueShare q = queue_share_for(t, o, x);
     std::priority_queue<double, std::vector<double>, std::greater<double>> freeq;
     for (int64_t i = 0; i < wgs; ++i) freeq.push(0.0);
-    auto take = [&](double c) {
-      const double t = freeq.top() + c;
+    for (int64_t it = 0; it < q.n_items; ++it) {
+      const int64_t i = share_item(q, it);
+      const double c = i < full ? cost[(size_t)i] : cost[(size_t)(full + (i - full) / ks)] / (double)ks + kSegmentOverhead;
+      const double t_end = freeq.top() + c;
       freeq.pop();
-      freeq.push(t);
-      makespan = std::max(makespan, t);
-    };
-    const int64_t m_lo = std::min(x * per_m, full), m_hi = std::min(m_lo + per_m, full);
-    for (int64_t i = m_lo; i < m_hi; ++i) take(cost[i]);
-    const int64_t t_lo = std::min(x * per_t, nseg), t_hi = std::min(t_lo + per_t, nseg);
-    for (int64_t j = t_lo; j < t_hi; ++j) take(cost[full + j / ks] / (double)ks + kSegmentOverhead);
+      freeq.push(t_end);
+      makespan = std::max(makespan, t_end);
+    }
   }
+  (void)tiles;
   return makespan;
 }
 
@@ -93,23 +107,29 @@ int64_t plan_schedule(const TileGeom& g, int64_t nkt, int64_t resident, int min_
   t->counters = counters;
   t->queue = counters + kTailMaxSegments;
   if (allow_split && ws && tiles > 0) {
-    const auto key = std::make_tuple(g.M, g.N, nkt, g.bm, g.bn, g.wgm, g.wgn, resident, min_kt_per_seg, allow_split);
+    const auto key = std::make_tuple(g.M, g.N, nkt, g.bm, g.bn, g.wgm, g.wgn * 1000 + g.narrow_cols, resident,
+                                     min_kt_per_seg, allow_split);
     PlanCache& pc = plan_cache();
     std::lock_guard<std::mutex> lock(pc.mu);
     auto it = pc.plans.find(key);
     if (it == pc.plans.end()) {
       std::vector<double> cost((size_t)tiles);
-      for (int64_t i = 0; i < tiles; ++i) cost[(size_t)i] = tile_cost(g, tiles_n, i);
+      for (int64_t i = 0; i < tiles; ++i) cost[(size_t)i] = tile_cost(g, i);
       int64_t best_full = tiles, best_ks = 1;
-      double best = simulate(g, tiles_n, tiles, tiles, 1, grid_for(resident, tiles, 0), cost);
-      // split the tiles of the last round, or of the last round and a half
+      double best = simulate(g, tiles, tiles, 1, grid_for(resident, tiles, 0), cost);
+      // split the last r tiles: the last partial round, plus up to all the
+      // rest in steps of an eighth of a round (cheap edge tiles can leave
+      // whole tiles as the critical path)
       const int64_t rem = tiles % resident;
-      for (int64_t r : {rem, rem + resident / 2}) {
+      std::vector<int64_t> cands;
+      for (int64_t r = rem; r < tiles; r += std::max<int64_t>(1, resident / 8)) cands.push_back(r);
+      cands.push_back(tiles);
+      for (int64_t r : cands) {
         if (r <= 0 || r > tiles) continue;
         for (int64_t ks = 2; ks <= 8; ++ks) {
           if (nkt < (int64_t)min_kt_per_seg * ks || r * ks > kTailMaxSegments) break;
           const int64_t full = tiles - r;
-          const double m = simulate(g, tiles_n, tiles, full, ks, grid_for(resident, full, r * ks), cost);
+          const double m = simulate(g, tiles, full, ks, grid_for(resident, full, r * ks), cost);
           if (m < best - 1e-6) {
             best = m;
             best_full = full;

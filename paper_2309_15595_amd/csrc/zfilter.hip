@@ -257,13 +257,13 @@ __device__ __forceinline__ void zbig_tile(const GemmArgs& g, int64_t tm, int64_t
 // applies the epilogue and resets the tile's counter for the next launch.
 template <class P, int WGM, int WGN, int TM, int TN, int BK>
 __device__ __forceinline__ void zbig_arrive(const GemmArgs& g, const TailSplit& tail, const WorkItem& w,
-                                            int64_t tiles_n, int* last) {
+                                            int* last) {
   using C = Cfg<WGM, WGN, TM, TN, BK>;
   using zv = typename P::cplx;
   using real = typename P::real;
   constexpr int BM = C::BM, BN = C::BN;
   const int64_t tl = w.seg / tail.ksplit;
-  const int64_t tm = w.tile / tiles_n, tn = w.tile % tiles_n;
+  const int64_t tm = w.tm, tn = w.tn;
   __threadfence();
   if (wg_fetch_add(tail.counters + tl, 1, last) != tail.ksplit - 1) return;
   __threadfence();
@@ -306,13 +306,13 @@ __device__ __forceinline__ void zbig_body(const GemmArgs& g, const TailSplit& ta
   constexpr int BM = C::BM, BN = C::BN;
   __shared__ Smem<P, C, BK> s;
   __shared__ int last, item;
-  const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const QueueShare q = queue_share(tail, ((g.M + BM - 1) / BM) * tiles_n);
+  const TileOrder o = tile_order(g.M, g.N, BM, BN);
+  const QueueShare q = queue_share(tail, o);
   for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
-    const WorkItem w = work_item(tail, i, g.K, BK);
+    const WorkItem w = work_item(tail, o, i, g.K, BK);
     zv* part = w.seg < 0 ? nullptr : reinterpret_cast<zv*>(tail.ws) + w.seg * (int64_t)(BM * BN);
-    zbig_tile<P, WGM, WGN, TM, TN, BK>(g, w.tile / tiles_n, w.tile % tiles_n, s, w.kbeg, w.kend, part);
-    if (w.seg >= 0) zbig_arrive<P, WGM, WGN, TM, TN, BK>(g, tail, w, tiles_n, &last);
+    zbig_tile<P, WGM, WGN, TM, TN, BK>(g, w.tm, w.tn, s, w.kbeg, w.kend, part);
+    if (w.seg >= 0) zbig_arrive<P, WGM, WGN, TM, TN, BK>(g, tail, w, &last);
   }
   queue_leave(tail);
 }
@@ -382,10 +382,23 @@ __device__ __forceinline__ void dz_issue(const GemmArgs& g, int64_t m0, int64_t 
   }
 }
 
-template <bool EDGE>
+// Wave layout: LWGM waves along m of LTM 16-row blocks each, 8 / LWGM waves
+// along n of two 16-column blocks each.  The main layout is 2 x 4 waves of
+// 64 x 32.  A last column tile with at most 32 live columns uses 8 x 1 waves
+// of 16 x 32, which puts two busy waves on every SIMD (a quarter of a tile's
+// time) instead of one busy wave on two SIMDs (half of it); one with at most
+// 64 uses 4 x 2 waves of 32 x 32 (half a tile, with two busy waves per SIMD to
+// cover each other's LDS and barrier waits instead of one).
+template <bool EDGE, int LWGM, int LTM>
 __device__ __forceinline__ void zdma_tile_impl(const GemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg, int64_t kend,
                                                zv* part, unsigned char* lds) {
-  using namespace dz;
+  using dz::BM;
+  using dz::BN;
+  using dz::BK;
+  using dz::A_BYTES;
+  using dz::STAGE;
+  constexpr int WGM = LWGM, TM = LTM, WGN = 8 / LWGM, TN = 2;
+  static_assert(WGM * TM * 16 == BM && WGN * TN * 16 <= BN, "wave layout");
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -494,17 +507,21 @@ __device__ __forceinline__ void zdma_body(const GemmArgs& g, const TailSplit& ta
   using namespace dz;
   __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
   __shared__ int last, item;
-  const int64_t tiles_n = (g.N + BN - 1) / BN;
-  const QueueShare q = queue_share(tail, ((g.M + BM - 1) / BM) * tiles_n);
+  const TileOrder o = tile_order(g.M, g.N, BM, BN);
+  const QueueShare q = queue_share(tail, o);
   for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
-    const WorkItem w = work_item(tail, i, g.K, BK);
+    const WorkItem w = work_item(tail, o, i, g.K, BK);
     zv* part = w.seg < 0 ? nullptr : reinterpret_cast<zv*>(tail.ws) + w.seg * (int64_t)(BM * BN);
-    const int64_t tm = w.tile / tiles_n, tn = w.tile % tiles_n;
+    const int64_t tm = w.tm, tn = w.tn;
     if ((tm + 1) * BM <= g.M && (tn + 1) * BN <= g.N)
-      zdma_tile_impl<false>(g, tm, tn, w.kbeg, w.kend, part, lds);
+      zdma_tile_impl<false, WGM, TM>(g, tm, tn, w.kbeg, w.kend, part, lds);
+    else if (g.N - tn * BN <= 32)
+      zdma_tile_impl<true, 8, 1>(g, tm, tn, w.kbeg, w.kend, part, lds);
+    else if (g.N - tn * BN <= 64)
+      zdma_tile_impl<true, 4, 2>(g, tm, tn, w.kbeg, w.kend, part, lds);
     else
-      zdma_tile_impl<true>(g, tm, tn, w.kbeg, w.kend, part, lds);
-    if (w.seg >= 0) zbig_arrive<PF64, WGM, WGN, TM, TN, BK>(g, tail, w, tiles_n, &last);
+      zdma_tile_impl<true, WGM, TM>(g, tm, tn, w.kbeg, w.kend, part, lds);
+    if (w.seg >= 0) zbig_arrive<PF64, WGM, WGN, TM, TN, BK>(g, tail, w, &last);
   }
   queue_leave(tail);
 }
@@ -630,6 +647,7 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
   const CfgInfo& c = cfg == 1 ? kCfg[1] : kDma;
   TileGeom geo;
   geo.M = g.M; geo.N = g.N; geo.bm = c.bm; geo.bn = c.bn; geo.wgm = c.wgm; geo.wgn = c.wgn;
+  if (cfg == 0) geo.narrow_cols = 32;  // the direct-to-LDS step's narrow edge layout
   TailSplit t;
   const int64_t grid = plan_schedule(geo, cdiv(g.K, c.bk), (int64_t)cu_count() * c.wg_per_cu, 16,
                                      choice != kChoiceT0NoTail, tail_ws, tail_counters, &t);
