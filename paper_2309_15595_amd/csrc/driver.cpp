@@ -1158,6 +1158,7 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
   std::vector<ProblemState> ps(count);
   GroupEntry* h_table = nullptr;
   GroupEntry* d_table = nullptr;
+  int* d_queue = nullptr;  // work queue of the grouped filter launches
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1186,6 +1187,8 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
     const size_t tbytes = sizeof(GroupEntry) * (size_t)max_deg * count;
     CHASE_CHK(hipHostMalloc(reinterpret_cast<void**>(&h_table), tbytes, hipHostMallocDefault));
     CHASE_CHK(hipMalloc(reinterpret_cast<void**>(&d_table), tbytes));
+    CHASE_CHK(hipMalloc(reinterpret_cast<void**>(&d_queue), sizeof(int) * kQueueInts));
+    if ((st = queue_counters_init(d_queue, s))) return st;
     CHASE_CHK(hipGetDevice(&dev));
     for (int wk = 0; wk < nw; ++wk) CHASE_CHK(hipStreamCreate(&wstreams[wk]));
     CHASE_CHK(hipEventCreateWithFlags(&filtered, hipEventDisableTiming));
@@ -1244,7 +1247,7 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
         if ((st = build_table(c))) return st;
         CHASE_CHK(hipMemcpyAsync(d_table, h_table, tbytes, hipMemcpyHostToDevice, s));
         float ms = 1e30f;
-        if ((st = time_launches([&]() { return zfilter_grouped_launch(d_table, count, 0, grouped_grid(c), s, c); },
+        if ((st = time_launches([&]() { return zfilter_grouped_launch(d_table, count, 0, grouped_grid(c), s, c, d_queue); },
                                 s, &ms)))
           return st;
         if (ms < best_ms) {
@@ -1259,7 +1262,7 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
     CHASE_CHK(hipStreamCreate(&cs));
     CHASE_CHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < max_deg; ++k) {
-      if ((st = zfilter_grouped_launch(d_table, count, k, grid, cs, cfg))) {
+      if ((st = zfilter_grouped_launch(d_table, count, k, grid, cs, cfg, d_queue))) {
         hipGraph_t g2 = nullptr;
         (void)hipStreamEndCapture(cs, &g2);
         if (g2) (void)hipGraphDestroy(g2);
@@ -1325,6 +1328,7 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
     if (w) (void)hipStreamDestroy(w);
   if (filtered) (void)hipEventDestroy(filtered);
   if (d_table) (void)hipFree(d_table);
+  if (d_queue) (void)hipFree(d_queue);
   if (h_table) (void)hipHostFree(h_table);
   int worst = kOk;
   for (int i = 0; i < count; ++i) {

@@ -82,8 +82,13 @@ struct GroupEntry {
 // M x N output (tiles_n: column tiles).
 int64_t zfilter_tiles(int64_t M, int64_t N, int64_t* tiles_n, int cfg = 0);
 // Persistent grouped filter step over row `step` of a device table of
-// `count` entries per step; grid a multiple of 8 (see grouped_grid).
-int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s, int cfg = 0);
+// `count` entries per step; grid a multiple of 8 (see grouped_grid).  cfg 0
+// (128 x 128 direct-to-LDS tile) takes tiles from the work queue `queue`
+// (kQueueInts ints, zeroed once by queue_counters_init; launches sharing it
+// must be serialised); cfg 1 (128 x 64 staged tile) needs none.
+int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s, int cfg,
+                           int* queue);
+int queue_counters_init(int* queue, hipStream_t s);
 // Grid filling every CU with resident workgroups of configuration cfg.
 int grouped_grid(int cfg);
 // Split over K into `splits` partial products in `ws`, summed in fixed order;

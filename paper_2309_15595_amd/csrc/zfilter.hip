@@ -502,6 +502,20 @@ __device__ __forceinline__ void zdma_tile_impl(const GemmArgs& g, int64_t tm, in
       }
 }
 
+// One tile (or K range of one) in the layout its live region calls for.
+__device__ __forceinline__ void zdma_tile(const GemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg, int64_t kend,
+                                          zv* part, unsigned char* lds) {
+  using namespace dz;
+  if ((tm + 1) * BM <= g.M && (tn + 1) * BN <= g.N)
+    zdma_tile_impl<false, WGM, TM>(g, tm, tn, kbeg, kend, part, lds);
+  else if (g.N - tn * BN <= 32)
+    zdma_tile_impl<true, 8, 1>(g, tm, tn, kbeg, kend, part, lds);
+  else if (g.N - tn * BN <= 64)
+    zdma_tile_impl<true, 4, 2>(g, tm, tn, kbeg, kend, part, lds);
+  else
+    zdma_tile_impl<true, WGM, TM>(g, tm, tn, kbeg, kend, part, lds);
+}
+
 // Whole launch of the direct-to-LDS step on the per-XCD work queue.
 __device__ __forceinline__ void zdma_body(const GemmArgs& g, const TailSplit& tail) {
   using namespace dz;
@@ -512,15 +526,7 @@ __device__ __forceinline__ void zdma_body(const GemmArgs& g, const TailSplit& ta
   for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
     const WorkItem w = work_item(tail, o, i, g.K, BK);
     zv* part = w.seg < 0 ? nullptr : reinterpret_cast<zv*>(tail.ws) + w.seg * (int64_t)(BM * BN);
-    const int64_t tm = w.tm, tn = w.tn;
-    if ((tm + 1) * BM <= g.M && (tn + 1) * BN <= g.N)
-      zdma_tile_impl<false, WGM, TM>(g, tm, tn, w.kbeg, w.kend, part, lds);
-    else if (g.N - tn * BN <= 32)
-      zdma_tile_impl<true, 8, 1>(g, tm, tn, w.kbeg, w.kend, part, lds);
-    else if (g.N - tn * BN <= 64)
-      zdma_tile_impl<true, 4, 2>(g, tm, tn, w.kbeg, w.kend, part, lds);
-    else
-      zdma_tile_impl<true, WGM, TM>(g, tm, tn, w.kbeg, w.kend, part, lds);
+    zdma_tile(g, w.tm, w.tn, w.kbeg, w.kend, part, lds);
     if (w.seg >= 0) zbig_arrive<PF64, WGM, WGN, TM, TN, BK>(g, tail, w, &last);
   }
   queue_leave(tail);
@@ -554,6 +560,41 @@ __device__ __forceinline__ void zbig_grouped(const GroupEntry* __restrict__ tabl
   }
 }
 
+// Grouped step for many problems at once, on the direct-to-LDS tile: row
+// `step` of the descriptor table lists one GEMM per problem with its tile
+// count as a running prefix sum.  A persistent grid takes the step's tiles
+// (all problems, problem by problem) from per-XCD counters; every parameter
+// comes from device memory, so a captured graph of these launches stays
+// valid while degrees, columns and scalars change.  A step with no work
+// still passes through the queue, so the counters are always reset.
+__device__ __forceinline__ void zdma_grouped_body(const GroupEntry* __restrict__ table, int count, int step,
+                                                  int* queue) {
+  using namespace dz;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+  __shared__ int item;
+  const GroupEntry* __restrict__ row = table + (int64_t)step * count;
+  TailSplit t;
+  t.full = row[count - 1].tile_end;
+  t.ksplit = 1;
+  t.queue = queue;
+  TileOrder all;
+  all.tiles_m = t.full;
+  all.tiles_n = 1;
+  all.edge_last = false;
+  const QueueShare q = queue_share(t, all);
+  int p = 0;
+  for (int64_t i; (i = queue_next(t, q, &item)) >= 0;) {
+    while (row[p].tile_end <= i) ++p;  // items arrive in increasing order
+    p = __builtin_amdgcn_readfirstlane(p);
+    const int64_t begin = p > 0 ? row[p - 1].tile_end : 0;
+    const GemmArgs g = row[p].g;
+    int64_t tm, tn;
+    tile_rc(tile_order(g.M, g.N, BM, BN), i - begin, &tm, &tn);
+    zdma_tile(g, tm, tn, 0, g.K, nullptr, lds);
+  }
+  queue_leave(t);
+}
+
 // Tile configurations (waves along m, waves along n, 16-blocks per wave
 // along m and n, K tile):
 //   T0: 128 x 128 complex tile, 8 waves of 64 x 32, one workgroup per CU;
@@ -576,9 +617,9 @@ __global__ __launch_bounds__(dz::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit 
 #define TF32_ARGS 2, 4, 4, 2, 16
 using CF = Cfg<TF32_ARGS>;
 __global__ __launch_bounds__(CF::NT, 1) void cfilter_step(GemmArgs g, TailSplit t) { zbig_body<PF32, TF32_ARGS>(g, t); }
-__global__ __launch_bounds__(C0::NT, 1) void zfilter_grouped(const GroupEntry* __restrict__ table, int count,
-                                                             int step) {
-  zbig_grouped<T0_ARGS>(table, count, step);
+__global__ __launch_bounds__(dz::NT, 1) void zfilter_grouped(const GroupEntry* __restrict__ table, int count,
+                                                             int step, int* queue) {
+  zdma_grouped_body(table, count, step, queue);
 }
 __global__ __launch_bounds__(C1::NT, 2) void zfilter_grouped_n64(const GroupEntry* __restrict__ table, int count,
                                                                  int step) {
@@ -617,12 +658,15 @@ int64_t zfilter_tiles(int64_t M, int64_t N, int64_t* tiles_n, int cfg) {
   return cdiv(M, c.bm) * cdiv(N, c.bn);
 }
 
-int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s, int cfg) {
+int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int grid, hipStream_t s, int cfg,
+                           int* queue) {
   if (count <= 0 || grid <= 0 || grid % 8) return -1;
   if (cfg == 1)
     hipLaunchKernelGGL(zfilter_grouped_n64, dim3((unsigned)grid), dim3(C1::NT), 0, s, table, count, step);
+  else if (queue == nullptr)
+    return -1;
   else
-    hipLaunchKernelGGL(zfilter_grouped, dim3((unsigned)grid), dim3(C0::NT), 0, s, table, count, step);
+    hipLaunchKernelGGL(zfilter_grouped, dim3((unsigned)grid), dim3(dz::NT), 0, s, table, count, step, queue);
   CHASE_CHK_LAUNCH();
   return kOk;
 }
@@ -630,6 +674,12 @@ int zfilter_grouped_launch(const GroupEntry* table, int count, int step, int gri
 int grouped_grid(int cfg) { return (int)(8 * cdiv((int64_t)cu_count() * kCfg[cfg & 1].wg_per_cu, 8)); }
 
 int64_t tail_workspace_bytes() { return (int64_t)kTailMaxSegments * C0::BM * C0::BN * 16; }
+
+int queue_counters_init(int* queue, hipStream_t s) {
+  hipLaunchKernelGGL(counters_zero, dim3(1), dim3(64), 0, s, queue, kQueueInts);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
 
 int tail_counters_init(int* counters, hipStream_t s) {
   hipLaunchKernelGGL(counters_zero, dim3((kTailCounterInts + 255) / 256), dim3(256), 0, s, counters,
