@@ -1054,7 +1054,7 @@ int chase_default_params(chase_params_t* p) {
   p->bounds_given = 0;
   p->tol = 1e-10;
   p->mixed_switch = 1e-6;
-  p->bf16_switch = 1e-4;
+  p->bf16_switch = 1e-5;
   p->seed = 2309;
   return 0;
 }
