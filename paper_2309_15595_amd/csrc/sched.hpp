@@ -161,8 +161,13 @@ __device__ __forceinline__ int wg_fetch_add(int* counter, int add, int* sh) {
 // XCD's share is exhausted.  Called by every thread; item_sh is LDS.
 __device__ __forceinline__ int64_t queue_next(const TailSplit& tail, const QueueShare& q, int* item_sh) {
   const int64_t it = wg_fetch_add(tail.queue + q.xcd, 1, item_sh);
-  if (it >= q.n_items) return -1;
-  return share_item(q, it);
+  const int64_t i = it >= q.n_items ? -1 : share_item(q, it);
+  // uniform in fact; made uniform for the compiler too, so the item loop's
+  // exit is a scalar branch in every instantiation (see wg_fetch_add)
+  const uint64_t u = (uint64_t)i;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // The workgroup is done with the launch; the last one clears the queue.

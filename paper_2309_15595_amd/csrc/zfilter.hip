@@ -560,6 +560,190 @@ __device__ __forceinline__ void zbig_grouped(const GroupEntry* __restrict__ tabl
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 step (mixed precision) with direct-to-LDS operand loads: the FP64
+// schedule on complex64 data.  One 16-byte DMA lane carries two complex64
+// values, so
+//   H: [k][m], 1 KB per k row; one instruction moves the 128 rows of one
+//      column of H (two rows per lane);
+//   X: [n][chunk ^ (n mod 16)] in 16-byte chunks of two consecutive k, 256 B
+//      per column (K-tile 32); one instruction moves 4 columns.
+// The pairs never straddle the end of a row range or of K when M, K, the
+// leading dimensions and every segment boundary are even and the operands
+// 16-byte aligned; the launcher checks this and otherwise runs the staged
+// FP32 kernel.  k beyond the K range is written as zero.
+// ---------------------------------------------------------------------------
+namespace dc {
+constexpr int BM = 128, BN = 128, BK = 32, NT = 512;
+constexpr int WGM = 2, WGN = 4, TM = 4, TN = 2;
+constexpr int A_ROW = BM * 8;
+constexpr int A_BYTES = BK * A_ROW;
+constexpr int B_COL = BK * 8;
+constexpr int B_BYTES = BN * B_COL;
+constexpr int STAGE = A_BYTES + B_BYTES;
+}  // namespace dc
+
+template <bool EDGE>
+__device__ __forceinline__ void dc_issue(const GemmArgs& g, int64_t m0, int64_t n0, int64_t k0, int64_t kend,
+                                         unsigned char* stage, int wave, int lane) {
+  using namespace dc;
+  using cv = PF32::cplx;
+  const cv* A = reinterpret_cast<const cv*>(g.A);
+  const cv* B = reinterpret_cast<const cv*>(g.B);
+  const bool kfull = k0 + BK <= kend;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int kr = wave * 4 + r;  // one k row of 128 rows of H
+    const int64_t k = k0 + kr;
+    unsigned char* dst = stage + kr * A_ROW;
+    const int64_t m = m0 + 2 * lane;
+    if (kfull || k < kend) {
+      if (!EDGE || m < g.M) __builtin_amdgcn_global_load_lds(A + m + k * g.lda, dst, 16, 0, 0);
+    } else {
+      reinterpret_cast<uint4*>(dst)[lane] = uint4{0u, 0u, 0u, 0u};
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ib = wave * 4 + r;  // columns 4 ib .. 4 ib + 3
+    const int nl = ib * 4 + (lane >> 4);
+    const int c = (lane & 15) ^ (nl & 15);  // chunk of k pair 2c, 2c + 1
+    const int64_t n = n0 + nl, k = k0 + 2 * c;
+    unsigned char* dst = stage + A_BYTES + ib * 1024;
+    if (kfull || k < kend) {
+      if (!EDGE || n < g.N) __builtin_amdgcn_global_load_lds(B + k + n * g.ldb, dst, 16, 0, 0);
+    } else {
+      reinterpret_cast<uint4*>(dst)[lane] = uint4{0u, 0u, 0u, 0u};
+    }
+  }
+}
+
+template <bool EDGE>
+__device__ __forceinline__ void cdma_tile_impl(const GemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg, int64_t kend,
+                                               PF32::cplx* part, unsigned char* lds) {
+  using namespace dc;
+  using cv = PF32::cplx;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const bool active = !EDGE || (m0 + wm * TM * 16 < g.M && n0 + wn * TN * 16 < g.N);
+  const int issue_at = wave < 4 ? 0 : BK / 8;  // waves w and w + 4 share a SIMD
+  f32x4 cr[TN][TM], ci[TN][TM];
+#pragma unroll
+  for (int a = 0; a < TN; ++a)
+#pragma unroll
+    for (int b = 0; b < TM; ++b) {
+      cr[a][b] = f32x4{0, 0, 0, 0};
+      ci[a][b] = f32x4{0, 0, 0, 0};
+    }
+  const int64_t nkt = (kend - kbeg + BK - 1) / BK;
+  if (nkt > 0) dc_issue<EDGE>(g, m0, n0, kbeg, kend, lds, wave, lane);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const unsigned char* cur = lds + (kt & 1) * STAGE;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      if (ks == issue_at && kt + 1 < nkt)
+        dc_issue<EDGE>(g, m0, n0, kbeg + (kt + 1) * BK, kend, lds + ((kt + 1) & 1) * STAGE, wave, lane);
+      if (!active) continue;
+      const int kk = ks * 4 + kq;
+      float br[TN], bi[TN], ar[TM], ai[TM];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = wn * TN * 16 + j * 16 + l16;
+        const cv v = *reinterpret_cast<const cv*>(cur + A_BYTES + n * B_COL + (((kk >> 1) ^ (n & 15)) << 4) +
+                                                  ((kk & 1) << 3));
+        br[j] = v.re;
+        bi[j] = v.im;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int m = wm * TM * 16 + i * 16 + l16;
+        const cv v = *reinterpret_cast<const cv*>(cur + kk * A_ROW + (m << 3));
+        ar[i] = v.re;
+        ai[i] = v.im;
+      }
+#pragma unroll
+      for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < TM; ++mb) {
+          cr[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(br[nb], ar[mb], cr[nb][mb], 0, 0, 0);
+          ci[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(br[nb], ai[mb], ci[nb][mb], 0, 0, 0);
+        }
+#pragma unroll
+      for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < TM; ++mb) {
+          cr[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-bi[nb], ai[mb], cr[nb][mb], 0, 0, 0);
+          ci[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(bi[nb], ar[mb], ci[nb][mb], 0, 0, 0);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next K-tile have landed
+    __syncthreads();
+  }
+
+  if (part != nullptr) {
+#pragma unroll
+    for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+      for (int mb = 0; mb < TM; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int nl = wn * TN * 16 + nb * 16 + PF32::row(kq, r);
+          const int ml = wm * TM * 16 + mb * 16 + l16;
+          part[ml + nl * BM] = cv{cr[nb][mb][r], ci[nb][mb][r]};
+        }
+    return;
+  }
+  cv* Y = reinterpret_cast<cv*>(g.Y);
+  const cv* Z = reinterpret_cast<const cv*>(g.Z);
+  const float al = (float)g.alpha, be = (float)g.beta, ga = (float)g.gamma;
+#pragma unroll
+  for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+    for (int mb = 0; mb < TM; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t n = n0 + wn * TN * 16 + nb * 16 + PF32::row(kq, r);
+        const int64_t m = m0 + wm * TM * 16 + mb * 16 + l16;
+        if (m >= g.M || n >= g.N) continue;
+        cv out{al * cr[nb][mb][r], al * ci[nb][mb][r]};
+        if (g.beta != 0.0) {
+          const cv y = Y[m + n * g.ldy];
+          out.re += be * y.re;
+          out.im += be * y.im;
+        }
+        if (g.gamma != 0.0) {
+          const cv z = Z[m + n * g.ldz];
+          out.re += ga * z.re;
+          out.im += ga * z.im;
+        }
+        Y[m + n * g.ldy] = out;
+      }
+}
+
+// Whole launch of the direct-to-LDS FP32 step on the per-XCD work queue.
+__device__ __forceinline__ void cdma_body(const GemmArgs& g, const TailSplit& tail) {
+  using namespace dc;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+  __shared__ int last, item;
+  const TileOrder o = tile_order(g.M, g.N, BM, BN);
+  const QueueShare q = queue_share(tail, o);
+  for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
+    const WorkItem w = work_item(tail, o, i, g.K, BK);
+    PF32::cplx* part = w.seg < 0 ? nullptr : reinterpret_cast<PF32::cplx*>(tail.ws) + w.seg * (int64_t)(BM * BN);
+    if ((w.tm + 1) * BM <= g.M && (w.tn + 1) * BN <= g.N)
+      cdma_tile_impl<false>(g, w.tm, w.tn, w.kbeg, w.kend, part, lds);
+    else
+      cdma_tile_impl<true>(g, w.tm, w.tn, w.kbeg, w.kend, part, lds);
+    if (w.seg >= 0) zbig_arrive<PF32, WGM, WGN, TM, TN, BK>(g, tail, w, &last);
+  }
+  queue_leave(tail);
+}
+
 // Grouped step for many problems at once, on the direct-to-LDS tile: row
 // `step` of the descriptor table lists one GEMM per problem with its tile
 // count as a running prefix sum.  A persistent grid takes the step's tiles
@@ -617,6 +801,8 @@ __global__ __launch_bounds__(dz::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit 
 #define TF32_ARGS 2, 4, 4, 2, 16
 using CF = Cfg<TF32_ARGS>;
 __global__ __launch_bounds__(CF::NT, 1) void cfilter_step(GemmArgs g, TailSplit t) { zbig_body<PF32, TF32_ARGS>(g, t); }
+// direct-to-LDS FP32 step (even M, K, leading dimensions)
+__global__ __launch_bounds__(dc::NT, 1) void cfilter_step_dma(GemmArgs g, TailSplit t) { cdma_body(g, t); }
 __global__ __launch_bounds__(dz::NT, 1) void zfilter_grouped(const GroupEntry* __restrict__ table, int count,
                                                              int step, int* queue) {
   zdma_grouped_body(table, count, step, queue);
@@ -726,11 +912,20 @@ int cfilter_big_launch(const CGemmArgs& c, hipStream_t s, void* tail_ws, int* ta
   g.Z = reinterpret_cast<const z64*>(c.Z); g.ldz = c.ldz;
   g.alpha = c.alpha; g.beta = c.beta; g.gamma = c.gamma;
   if (g.K <= 0) g.alpha = 0.0;
+  // two complex64 per 16-byte load: pairs must not straddle a row range, K
+  // or an alignment boundary
+  const bool dma = g.M % 2 == 0 && g.K % 2 == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 &&
+                   reinterpret_cast<uintptr_t>(c.A) % 16 == 0 && reinterpret_cast<uintptr_t>(c.B) % 16 == 0;
   TileGeom geo;
   geo.M = g.M; geo.N = g.N; geo.bm = CF::BM; geo.bn = CF::BN; geo.wgm = CF::WGM_; geo.wgn = CF::WGN_;
   TailSplit t;
-  const int64_t grid = plan_schedule(geo, cdiv(g.K, CF::BK_), cu_count(), 16, true, tail_ws, tail_counters, &t);
-  hipLaunchKernelGGL(cfilter_step, dim3((unsigned)grid), dim3(CF::NT), 0, s, g, t);
+  if (dma) {
+    const int64_t grid = plan_schedule(geo, cdiv(g.K, dc::BK), cu_count(), 8, true, tail_ws, tail_counters, &t);
+    hipLaunchKernelGGL(cfilter_step_dma, dim3((unsigned)grid), dim3(dc::NT), 0, s, g, t);
+  } else {
+    const int64_t grid = plan_schedule(geo, cdiv(g.K, CF::BK_), cu_count(), 16, true, tail_ws, tail_counters, &t);
+    hipLaunchKernelGGL(cfilter_step, dim3((unsigned)grid), dim3(CF::NT), 0, s, g, t);
+  }
   CHASE_CHK_LAUNCH();
   return kOk;
 }

@@ -88,7 +88,8 @@ def test_batched_rejects_mixed_precision(L):
 # ---------------------------------------------------------------- mixed precision
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("N,nev,nex,spectrum", [(800, 60, 20, "uniform"), (1200, 60, 15, "dft")])
+@pytest.mark.parametrize("N,nev,nex,spectrum", [(800, 60, 20, "uniform"), (1200, 60, 15, "dft"),
+                                                (517, 40, 12, "uniform")])   # odd order: staged FP32 step
 def test_mixed_precision_reaches_fp64_accuracy(L, N, nev, nex, spectrum, prec):
     from paper_2309_15595_amd.api import Solver
     p = synth.make_problem(N, nev, nex, spectrum=spectrum, basis="gaussian", seed=N + 7)
