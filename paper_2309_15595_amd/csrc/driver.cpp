@@ -1364,7 +1364,7 @@ int chase_eigval_grad(int64_t N, int32_t nev, const void* X, int64_t ldx, const 
   a.bscale = g;
   a.Y = reinterpret_cast<z64*>(G); a.ldy = ldg;
   a.lower_only = fill == 1 ? 1 : 0;
-  return zgemm_launch(0, 1, a, s);
+  return zgrad_launch(a, s);
 }
 
 // ---- step entry points -------------------------------------------------------

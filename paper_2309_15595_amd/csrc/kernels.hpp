@@ -100,6 +100,11 @@ int zgemm_splitk(int opa, int opb, const GemmArgs& g, void* ws, int splits, int 
 int64_t zgemm_splitk_workspace(int64_t M, int64_t N, int splits);
 int choose_splits(int64_t M, int64_t N, int64_t K, int max_splits, bool lower = false);
 
+// G = X diag(s) X^H (zgrad.hip): g.A = g.B = X (M x K, ld), g.bscale = s (K,
+// device), g.Y = G; g.lower_only computes only the tiles that hold an element
+// on or below the diagonal (M == N).  Allocates nothing.
+int zgrad_launch(const GemmArgs& g, hipStream_t s);
+
 // Complex FP32 GEMM (mixed-precision filter): same contract with complex64 data.
 struct CGemmArgs {
   int64_t M = 0, N = 0, K = 0;
