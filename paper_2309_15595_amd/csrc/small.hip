@@ -288,6 +288,68 @@ __global__ __launch_bounds__(256) void hemv_kernel(const zv* A, int64_t lda, con
   }
 }
 
+// Four Lanczos vectors at once (the batched starts): W[:, c] = H^H V[:, c].
+// Each wave takes RPW columns of H (contiguous, coalesced) and each K chunk
+// of V is staged in LDS once for the workgroup's 4 * RPW columns, so V is
+// read from L2 once per workgroup instead of once per column (at one column
+// per wave the re-reads of V outweighed the stream of H five to one).  H is
+// read once from HBM.
+template <int NV, int RPW>
+__global__ __launch_bounds__(256) void hemv_panel_kernel(const zv* __restrict__ A, int64_t lda,
+                                                         const zv* __restrict__ V, int64_t ldv, zv* W,
+                                                         int64_t ldw, int64_t N) {
+  constexpr int KC = 256;  // k per chunk
+  __shared__ zv vs[NV][KC];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t m0 = ((int64_t)blockIdx.x * 4 + wave) * RPW;  // first column of this wave
+  double ar[RPW][NV], ai[RPW][NV];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) ar[r][c] = ai[r][c] = 0.0;
+  for (int64_t k0 = 0; k0 < N; k0 += KC) {  // every wave takes part in the barriers
+    __syncthreads();                         // the previous chunk has been used
+    for (int e = threadIdx.x; e < NV * KC; e += 256) {
+      const int c = e / KC, kk = e % KC;
+      const int64_t k = k0 + kk;
+      vs[c][kk] = k < N ? V[k + c * ldv] : zv{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < KC / 64; ++u) {
+      const int kk = u * 64 + lane;
+      const int64_t k = k0 + kk;
+      zv v[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) v[c] = vs[c][kk];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int64_t m = m0 + r;
+        if (m < N && k < N) {
+          const zv a = A[k + m * lda];  // conj(a) v
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+            ar[r][c] += a.re * v[c].re + a.im * v[c].im;
+            ai[r][c] += a.re * v[c].im - a.im * v[c].re;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double x = ar[r][c], y = ai[r][c];
+      for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_down(x, off, 64);
+        y += __shfl_down(y, off, 64);
+      }
+      const int64_t m = m0 + r;
+      if (lane == 0 && m < N) W[m + c * ldw] = zv{x, y};
+    }
+}
+
 __global__ __launch_bounds__(1024) void lanczos_init_kernel(const zv* S, int64_t ld, zv* V, zv* Vold, int64_t N) {
   __shared__ double red[17];
   const int64_t c = blockIdx.x;
@@ -518,6 +580,14 @@ int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N
 int hemv_block(const z64* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N, int nv,
                hipStream_t s) {
   if (nv < 1 || nv > 8) return -1;
+  if (nv == 4) {
+    constexpr int RPW = 4;
+    hipLaunchKernelGGL((hemv_panel_kernel<4, RPW>), dim3((unsigned)cdiv(N, 4 * RPW)), dim3(256), 0, s,
+                       reinterpret_cast<const zv*>(A), lda, reinterpret_cast<const zv*>(V), ldv,
+                       reinterpret_cast<zv*>(W), ldw, N);
+    CHASE_CHK_LAUNCH();
+    return kOk;
+  }
   hipLaunchKernelGGL(hemv_kernel, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, reinterpret_cast<const zv*>(A), lda,
                      reinterpret_cast<const zv*>(V), ldv, reinterpret_cast<zv*>(W), ldw, N, nv);
   CHASE_CHK_LAUNCH();
