@@ -120,7 +120,7 @@ int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h);
  *   stats  (host, nullable) */
 int chase_solve(chase_handle_t h, const void* A, int64_t lda, void* V, int64_t ldv, int32_t use_v0,
                 const void* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
-                chase_stats_t* stats, chase_stream_t stream);
+                chase_stats_t* stats, chase_stream_t stream);  /* -1: null or real handle */
 
 int chase_destroy(chase_handle_t h);
 
@@ -147,6 +147,35 @@ int chase_solve_batched(int32_t count, const int64_t* N, const void* const* A, c
  * Asynchronous on `stream` (allocates nothing). */
 int chase_eigval_grad(int64_t N, int32_t nev, const void* X, int64_t ldx, const double* g, void* G,
                       int64_t ldg, int32_t fill, chase_stream_t stream);
+
+/* ---- real symmetric H (the library's real type variant) ------------------
+ * The same method on a real symmetric matrix with real vectors: every
+ * matrix argument is a column-major double array (device, 16-byte aligned),
+ * and each filter MatVec costs 2 N^2 flops instead of 8 N^2.  Inside, a real
+ * column of even length is read as complex numbers of its row pairs, so the
+ * filter runs on a real variant of the complex kernel (real H read as
+ * complex row pairs times the real block) and the other steps on the complex
+ * kernels, keeping the real part where a product of two real blocks is
+ * formed.  FP64 only (params.precision must be CHASE_FP64). */
+
+/* Workspace for real symmetric problems of order N (any N >= 2): the complex
+ * buffers of chase_create at N/2 rows plus an internal copy of the block, an
+ * n_e x n_e real buffer and, for odd N or odd lda, a padded copy of H made at
+ * the first such solve.  A handle from here serves chase_solve_real only. */
+int chase_create_real(int64_t N, const chase_params_t* p, chase_handle_t* h);
+
+/* chase_solve for real symmetric A (N x N, full storage, read only): V
+ * (N x (nev+nex), in/out), starts (N x nstarts, nullable), ritzv and resid
+ * (host) as there.  Returns -1 for a handle not made by chase_create_real. */
+int chase_solve_real(chase_handle_t h, const double* A, int64_t lda, double* V, int64_t ldv, int32_t use_v0,
+                     const double* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
+                     chase_stats_t* stats, chase_stream_t stream);
+
+/* chase_filter on real data; N, lda, ldv and ldw must be even (-7, -2, -4,
+ * -6 otherwise). */
+int chase_filter_real(const double* A, int64_t lda, double* V, int64_t ldv, double* W, int64_t ldw, int64_t N,
+                      int64_t n, const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs,
+                      chase_stream_t stream);
 
 /* ---- steps of the loop, exposed for element-wise checks ------------------
  * These run one step of Alg. 2 exactly as chase_solve does. */
@@ -180,6 +209,37 @@ int chase_lanczos(const void* A, int64_t lda, int64_t N, const void* starts, int
 /* Alg. 5: condition-number estimate (host computation). */
 double chase_cond_est(const double* lam, double c, double e, const int32_t* degs, int32_t ne,
                       int32_t locked);
+
+/* ---- per-iteration trace (Sec. 4.2 and 4.3: CondEst against the computed
+ * condition number of the filtered vectors, QR variant and phase times per
+ * outer iteration) ----------------------------------------------------------- */
+#define CHASE_TRACE_MAX 256
+typedef struct {
+  int32_t iteration;       /* 1-based outer iteration */
+  int32_t locked;          /* pairs locked when the iteration started */
+  int32_t n_active;        /* columns filtered */
+  int32_t qr_variant;      /* CHASE_QR_* that produced the basis (after escalation) */
+  int64_t filter_matvecs;  /* sum of this iteration's filter degrees */
+  double kappa_est;        /* Alg. 5 estimate for the filtered block */
+  /* Trace level 2, else NaN: sigma_max / sigma_min of the n_e columns 1D-CAQR
+   * receives (locked and filtered); of the filtered columns alone; of all n_e
+   * columns scaled to unit norm (CholeskyQR is invariant to column scaling,
+   * so this is the figure its accuracy depends on). */
+  double kappa_com, kappa_com_active, kappa_com_equil;
+  double t_filter, t_qr, t_rr;  /* seconds, HIP events on the solve's stream */
+} chase_trace_t;
+
+/* Trace the next chase_solve calls on h: level 0 off (default), 1 records a
+ * chase_trace_t per outer iteration, 2 also computes the kappa_com figures
+ * from singular values of the block before each CAQR (rocSOLVER SVDs of an
+ * N x n_e copy: expensive, for studies only; the copy uses the handle's
+ * workspace and does not change the iteration).  At most CHASE_TRACE_MAX
+ * iterations are kept.  Returns -1 for a null handle, -2 for a bad level. */
+int chase_set_trace(chase_handle_t h, int32_t level);
+
+/* Copies up to cap records of the last traced solve on h to out (host);
+ * *count (host) receives the number copied. */
+int chase_get_trace(chase_handle_t h, chase_trace_t* out, int32_t cap, int32_t* count);
 
 const char* chase_status_string(int status);
 const char* chase_last_error(void);

@@ -52,6 +52,20 @@ class chase_stats_t(C.Structure):
         return d
 
 
+class chase_trace_t(C.Structure):
+    _fields_ = [
+        ("iteration", C.c_int32), ("locked", C.c_int32), ("n_active", C.c_int32),
+        ("qr_variant", C.c_int32), ("filter_matvecs", C.c_int64), ("kappa_est", C.c_double),
+        ("kappa_com", C.c_double), ("kappa_com_active", C.c_double), ("kappa_com_equil", C.c_double),
+        ("t_filter", C.c_double), ("t_qr", C.c_double), ("t_rr", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+CHASE_TRACE_MAX = 256
+
 _I64, _I32, _D, _P = C.c_int64, C.c_int32, C.c_double, C.c_void_p
 _DP = C.POINTER(C.c_double)
 _I32P = C.POINTER(C.c_int32)
@@ -74,6 +88,13 @@ SIGNATURES = {
     "chase_rayleigh_ritz": (C.c_int, [_P, _I64, _P, _I64, _I64, _I64, _DP, _DP, _P]),
     "chase_lanczos": (C.c_int, [_P, _I64, _I64, _P, _I64, _I32, _I32, _I32, _DP, _P]),
     "chase_cond_est": (C.c_double, [_DP, _D, _D, _I32P, _I32, _I32]),
+    "chase_create_real": (C.c_int, [_I64, C.POINTER(chase_params_t), C.POINTER(_P)]),
+    "chase_solve_real": (C.c_int, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _I32, _DP, _DP,
+                                   C.POINTER(chase_stats_t), _P]),
+    "chase_filter_real": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D,
+                                    _I64P, _P]),
+    "chase_set_trace": (C.c_int, [_P, _I32]),
+    "chase_get_trace": (C.c_int, [_P, C.POINTER(chase_trace_t), _I32, _I32P]),
     "chase_status_string": (C.c_char_p, [C.c_int]),
     "chase_last_error": (C.c_char_p, []),
 }
@@ -144,6 +165,30 @@ def chase_create(N: int, params: chase_params_t):
     h = _P()
     check(load().chase_create(N, C.byref(params), C.byref(h)), "chase_create")
     return h
+
+
+def chase_create_real(N: int, params: chase_params_t):
+    h = _P()
+    check(load().chase_create_real(N, C.byref(params), C.byref(h)), "chase_create_real")
+    return h
+
+
+def chase_solve_real(h, A_ptr, lda, V_ptr, ldv, use_v0, starts_ptr, ld_starts, nstarts, nev, stream):
+    ritz = f64_array(nev)
+    resid = f64_array(nev)
+    stats = chase_stats_t()
+    st = load().chase_solve_real(h, A_ptr, lda, V_ptr, ldv, use_v0, starts_ptr or None, ld_starts,
+                                 nstarts, ritz, resid, C.byref(stats), stream)
+    check(st, "chase_solve_real", allow_not_converged=True)
+    return list(ritz), list(resid), stats
+
+
+def chase_filter_real(A_ptr, lda, V_ptr, ldv, W_ptr, ldw, N, n, degs, c, e, mu_1, stream) -> int:
+    d = (C.c_int32 * n)(*[int(x) for x in degs])
+    mv = C.c_int64(0)
+    check(load().chase_filter_real(A_ptr, lda, V_ptr, ldv, W_ptr, ldw, N, n, d, c, e, mu_1,
+                                   C.byref(mv), stream), "chase_filter_real")
+    return mv.value
 
 
 def chase_destroy(h) -> None:

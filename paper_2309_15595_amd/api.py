@@ -44,15 +44,30 @@ class SolveInfo:
 class Solver:
     """A chase_create/chase_destroy handle for problems of order N."""
 
-    def __init__(self, N: int, nev: int, nex: int, **params):
-        self.N, self.nev, self.nex = N, nev, nex
+    def __init__(self, N: int, nev: int, nex: int, *, real: bool = False, **params):
+        """real=True: a real symmetric problem (float64 data, chase_create_real)."""
+        self.N, self.nev, self.nex, self.real = N, nev, nex, real
         self.params = _lib.default_params(nev=nev, nex=nex, **params)
-        self.h = _lib.chase_create(N, self.params)
+        self.h = (_lib.chase_create_real if real else _lib.chase_create)(N, self.params)
 
     def close(self):
         if self.h is not None:
             _lib.chase_destroy(self.h)
             self.h = None
+
+    def set_trace(self, level: int):
+        """Record a per-iteration trace of the following solves (level 1), with
+        the exact condition number of each filtered block (level 2)."""
+        _lib.check(_lib.load().chase_set_trace(self.h, int(level)), "chase_set_trace")
+
+    def trace(self):
+        """Per-iteration records of the last traced solve, as dicts."""
+        import ctypes
+        buf = (_lib.chase_trace_t * _lib.CHASE_TRACE_MAX)()
+        n = ctypes.c_int32(0)
+        _lib.check(_lib.load().chase_get_trace(self.h, buf, _lib.CHASE_TRACE_MAX, ctypes.byref(n)),
+                   "chase_get_trace")
+        return [buf[i].as_dict() for i in range(n.value)]
 
     def __enter__(self):
         return self
@@ -71,12 +86,14 @@ class Solver:
         """A_cm: (N, N) tensor holding A column-major; V_cm: (n_e, N) tensor
         holding the N x n_e block column-major (in/out)."""
         N = self.N
-        _check_dev(A_cm, (N, N))
-        _check_dev(V_cm, (self.nev + self.nex, N))
+        dt = torch.float64 if self.real else torch.complex128
+        _check_dev(A_cm, (N, N), dt)
+        _check_dev(V_cm, (self.nev + self.nex, N), dt)
         ns = 0 if starts_cm is None else starts_cm.shape[0]
         if starts_cm is not None:
-            _check_dev(starts_cm, (ns, N))
-        ritz, resid, stats = _lib.chase_solve(
+            _check_dev(starts_cm, (ns, N), dt)
+        solve = _lib.chase_solve_real if self.real else _lib.chase_solve
+        ritz, resid, stats = solve(
             self.h, _lib.dptr(A_cm), N, _lib.dptr(V_cm), N, int(use_v0), _lib.dptr(starts_cm),
             N, ns, self.nev, _lib.stream_ptr(stream))
         return np.array(ritz), np.array(resid), SolveInfo(stats.status == 0, stats.status,
@@ -105,11 +122,11 @@ def solve_batched(A_cms, V_cms, nevs, nexs, starts_cms=None, stream=None, **para
             [s.as_dict() for s in stats], st)
 
 
-def _check_dev(t: torch.Tensor, shape):
+def _check_dev(t: torch.Tensor, shape, dtype=torch.complex128):
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError("expected a CUDA (HIP) tensor")
-    if t.dtype != torch.complex128:
-        raise TypeError(f"expected complex128, got {t.dtype}")
+    if t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
     if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
         raise ValueError(f"expected a contiguous tensor of shape {shape}, got {tuple(t.shape)}")
 
@@ -117,14 +134,34 @@ def _check_dev(t: torch.Tensor, shape):
 def eigsh(A: torch.Tensor, nev: int, nex: int, *, deg: int = 20, tol: float = 1e-10,
           opt: bool = True, max_deg: int = 36, max_iter: int = 25, V0=None, starts=None,
           precision: str = "fp64", seed: int = 2309, return_raw: bool = False):
-    """nev lowest eigenpairs of the Hermitian (N, N) complex128 CUDA tensor A.
+    """nev lowest eigenpairs of the Hermitian (N, N) complex128 CUDA tensor A,
+    or of the real symmetric float64 one (then the real path, real vectors).
 
-    Returns (evals (nev,) float64 tensor, evecs (N, nev) complex128 tensor,
+    Returns (evals (nev,) float64 tensor, evecs (N, nev) tensor of A's dtype,
     SolveInfo).  V0 (N, nev+nex) optional initial block, starts (N, r)
     optional Lanczos start vectors.
     """
     N = A.shape[0]
     ne = nev + nex
+    if A.dtype == torch.float64:
+        if precision != "fp64":
+            raise ValueError("the real symmetric path is FP64 only")
+        _check_dev(A, (N, N), torch.float64)
+        with Solver(N, nev, nex, real=True, deg=deg, tol=tol, opt=int(opt), max_deg=max_deg,
+                    max_iter=max_iter, seed=seed) as s:
+            # symmetric: the row-major memory is the column-major matrix
+            if V0 is not None:
+                Vt = V0.transpose(0, 1).contiguous()
+            else:
+                Vt = torch.empty((ne, N), dtype=torch.float64, device=A.device)
+            st = None if starts is None else starts.transpose(0, 1).contiguous()
+            ritz, resid, info = s.solve_colmajor(A, Vt, use_v0=V0 is not None, starts_cm=st)
+        info.stats["resid"] = resid
+        evals = torch.from_numpy(ritz).to(A.device)
+        evecs = Vt[:nev].transpose(0, 1)
+        if return_raw:
+            return evals, evecs, info, Vt
+        return evals, evecs, info
     _check_dev(A, (N, N))
     with Solver(N, nev, nex, deg=deg, tol=tol, opt=int(opt), max_deg=max_deg,
                 max_iter=max_iter, precision=_PRECISIONS[precision], seed=seed) as s:

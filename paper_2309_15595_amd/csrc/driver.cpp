@@ -221,6 +221,18 @@ struct Workspace {
   void* tail_ws = nullptr;     // split-K tail of the big GEMMs
   int* tail_counters = nullptr;
   z64* tune_scratch = nullptr; // autotuner output sink (N x ne), allocated on first use
+  // Real symmetric problems run on the row-pair view: a real column of even
+  // length 2 N is read as N complex values (rows 2 i, 2 i + 1 as Re, Im), so
+  // every column operation, and every product whose real part is the wanted
+  // real product, runs on the complex kernels unchanged.  N is then the
+  // number of row pairs and `rows` the order; an odd order gets one zero row.
+  bool real = false;
+  int64_t rows = 0;
+  double* Gr = nullptr;        // ne x ne real copy for the symmetric eigensolver
+  z64* Cint = nullptr;         // N x ne: the caller's block in the row-pair layout
+  double* Hpad = nullptr;      // 2N x 2N copy of H when its own layout does not fit
+  const double* Hr = nullptr;  // this solve's H (real, order rows) for the Lanczos products
+  int64_t ldhr = 0;
   rocblas_handle rb = nullptr;
   std::vector<void*> owned;
 
@@ -284,6 +296,21 @@ struct Workspace {
     }
     if (st) release();
     return st;
+  }
+
+  // Workspace of a real symmetric problem of order n_real (row-pair view).
+  int create_real(int64_t n_real, int ne_) {
+    int st = create((n_real + 1) / 2, ne_, false, true, false);
+    if (st) return st;
+    real = true;
+    rows = n_real;
+    st = st ? st : alloc(&Gr, (size_t)ne_ * ne_);
+    st = st ? st : alloc(&Cint, (size_t)N * ne_);
+    if (st) release();
+    return st;
+  }
+  int ensure_hpad() {
+    return Hpad ? kOk : alloc(&Hpad, (size_t)(2 * N) * (size_t)(2 * N));
   }
 
   void release() {
@@ -409,13 +436,24 @@ static std::vector<GemmArgs> plan_filter(const z64* A, int64_t lda, z64* V, int6
   return steps;
 }
 
+// The steps of plan_filter on the row-pair view of a real problem (N pairs):
+// the B operand is the same memory read as a real block of 2 N rows.
+static void as_real_steps(std::vector<GemmArgs>& steps) {
+  for (GemmArgs& g : steps) {
+    g.K = 2 * g.M;
+    g.ldb *= 2;
+  }
+}
+
 static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N,
                       int64_t n, const int32_t* degs, double c, double e, double mu1, int64_t* matvecs,
-                      int64_t* launches, hipStream_t s, void* tail_ws, int* tail_counters) {
-  const std::vector<GemmArgs> steps = plan_filter(A, lda, V, ldv, W, ldw, N, n, degs, c, e, mu1);
+                      int64_t* launches, hipStream_t s, void* tail_ws, int* tail_counters, bool real = false) {
+  std::vector<GemmArgs> steps = plan_filter(A, lda, V, ldv, W, ldw, N, n, degs, c, e, mu1);
+  if (real) as_real_steps(steps);
   int64_t mv = 0;
   for (const GemmArgs& g : steps) {
-    int st = zgemm_nn_big_launch(g, s, true, tail_ws, tail_counters);
+    int st = real ? dfilter_big_launch(g, s, tail_ws, tail_counters)
+                  : zgemm_nn_big_launch(g, s, true, tail_ws, tail_counters);
     if (st) return st;
     mv += g.N;
   }
@@ -492,7 +530,7 @@ static int gram(Workspace& w, const z64* X, int64_t ldx, int64_t n, hipStream_t 
   g.Y = w.G; g.ldy = n;
   // lower triangle only: the Cholesky factorisation and the shift read nothing else
   const int splits = choose_splits(n, n, w.N, w.max_splits, true);
-  return zgemm_splitk(1, 0, g, w.ws, splits, 2, s);
+  return zgemm_splitk(1, 0, g, w.ws, splits, w.real ? 3 : 2, s);
 }
 
 // X <- X R^{-1} with R = L^H from G = L L^H.  Returns 1 in *failed when the
@@ -501,7 +539,7 @@ static int chol_apply(Workspace& w, z64* X, int64_t ldx, int64_t n, bool shifted
                       hipStream_t s) {
   int st = kOk;
   if (shifted) {
-    st = add_cholqr_shift(w.G, n, n, w.N, w.shift, s);
+    st = add_cholqr_shift(w.G, n, n, w.real ? w.rows : w.N, w.shift, s);
     if (st) return st;
   }
   st = potrf_lower(w.G, n, n, w.info, nullptr, s);
@@ -536,6 +574,19 @@ static int cholqr_pass(Workspace& w, z64* X, int64_t ldx, int64_t n, bool shifte
 
 static int householder(Workspace& w, z64* X, int64_t ldx, int64_t n, hipStream_t s) {
   rocblas_set_stream(w.rb, s);
+  if (w.real) {  // the real block (a zero padding row stays zero)
+    double* Xr = reinterpret_cast<double*>(X);
+    double* tau = reinterpret_cast<double*>(w.tau);
+    rocblas_status r = rocsolver_dgeqrf(w.rb, (rocblas_int)(2 * w.N), (rocblas_int)n, Xr, (rocblas_int)(2 * ldx), tau);
+    if (r == rocblas_status_success)
+      r = rocsolver_dorgqr(w.rb, (rocblas_int)(2 * w.N), (rocblas_int)n, (rocblas_int)n, Xr, (rocblas_int)(2 * ldx),
+                           tau);
+    if (r != rocblas_status_success) {
+      set_msg("rocsolver_dgeqrf/dorgqr failed");
+      return kHipError;
+    }
+    return kOk;
+  }
   rocblas_status r = rocsolver_zgeqrf(w.rb, (rocblas_int)w.N, (rocblas_int)n,
                                       reinterpret_cast<rocblas_double_complex*>(X), (rocblas_int)ldx,
                                       reinterpret_cast<rocblas_double_complex*>(w.tau));
@@ -604,22 +655,40 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   g.A = A; g.lda = lda;
   g.B = Q; g.ldb = ldq;
   g.Y = w.B; g.ldy = N;
-  int st = zgemm_nn_big_launch(g, s, false, w.tail_ws, w.tail_counters);
+  int st;
+  if (w.real) {
+    g.K = 2 * N;
+    g.ldb = 2 * ldq;
+    st = dfilter_big_launch(g, s, w.tail_ws, w.tail_counters);
+  } else {
+    st = zgemm_nn_big_launch(g, s, false, w.tail_ws, w.tail_counters);
+  }
   if (st) return st;
   GemmArgs q;  // G = Q^H B, lower triangle (the eigensolver reads nothing else)
   q.M = n; q.N = n; q.K = N;
   q.A = Q; q.lda = ldq;
   q.B = w.B; q.ldb = N;
   q.Y = w.G; q.ldy = n;
-  st = zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits, true), 2, s);
+  st = zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits, true), w.real ? 3 : 2, s);
   if (st) return st;
   rocblas_set_stream(w.rb, s);
-  rocblas_status r = rocsolver_zheevd(w.rb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n,
-                                      reinterpret_cast<rocblas_double_complex*>(w.G), (rocblas_int)n, w.theta,
-                                      w.E, w.info);
-  if (r != rocblas_status_success) {
-    set_msg("rocsolver_zheevd failed");
-    return kHipError;
+  if (w.real) {  // real symmetric quotient: eigenvectors real, back in complex storage
+    if ((st = z_real_part(w.G, n, w.Gr, n, n, s))) return st;
+    rocblas_status r = rocsolver_dsyevd(w.rb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n, w.Gr,
+                                        (rocblas_int)n, w.theta, w.E, w.info);
+    if (r != rocblas_status_success) {
+      set_msg("rocsolver_dsyevd failed");
+      return kHipError;
+    }
+    if ((st = d_to_z(w.Gr, n, w.G, n, n, s))) return st;
+  } else {
+    rocblas_status r = rocsolver_zheevd(w.rb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n,
+                                        reinterpret_cast<rocblas_double_complex*>(w.G), (rocblas_int)n, w.theta,
+                                        w.E, w.info);
+    if (r != rocblas_status_success) {
+      set_msg("rocsolver_zheevd failed");
+      return kHipError;
+    }
   }
   GemmArgs b;  // V = Q W
   b.M = N; b.N = n; b.K = n;
@@ -643,12 +712,17 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
 static int lanczos(Workspace& w, const z64* A, int64_t lda, const z64* starts, int64_t lds, int nstarts,
                    int ksteps, int ne, double out[4], hipStream_t s) {
   const int64_t N = w.N;
-  ksteps = (int)std::min<int64_t>(ksteps, N);
+  const int64_t order = w.real ? w.rows : N;
+  ksteps = (int)std::min<int64_t>(ksteps, order);
   if (nstarts < 1 || nstarts > 8 || ksteps < 1 || ksteps > 256) return -1;
   int st = lanczos_init(starts, lds, w.lzV, w.lzVold, N, nstarts, s);
   if (st) return st;
   for (int j = 0; j < ksteps; ++j) {
-    st = hemv_block(A, lda, w.lzV, N, w.lzW, N, N, nstarts, s);
+    if (w.real)
+      st = symv_block(w.Hr, w.ldhr, reinterpret_cast<const double*>(w.lzV), 2 * N, reinterpret_cast<double*>(w.lzW),
+                      2 * N, w.rows, 2 * N, nstarts, s);
+    else
+      st = hemv_block(A, lda, w.lzV, N, w.lzW, N, N, nstarts, s);
     if (st) return st;
     st = lanczos_step(w.lzV, w.lzVold, w.lzW, N, nstarts, j, ksteps, w.lz_alpha, w.lz_beta, s);
     if (st) return st;
@@ -659,7 +733,7 @@ static int lanczos(Workspace& w, const z64* A, int64_t lda, const z64* starts, i
   CHASE_CHK(hipStreamSynchronize(s));
   for (double x : al)
     if (!std::isfinite(x)) return kBreakdown;
-  bounds_from_lanczos(al, be, nstarts, ksteps, N, ne, out);
+  bounds_from_lanczos(al, be, nstarts, ksteps, order, ne, out);
   return kOk;
 }
 
@@ -719,6 +793,55 @@ static bool valid_params(const chase_params_t* p) {
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// Exact condition number sigma_max / sigma_min of the N x n block X (trace
+// level 2): singular values of a copy in the workspace (rocSOLVER SVD, no
+// vectors).  With `equilibrate` the copy's columns are scaled to unit norm
+// first.  w.B holds the copy; w.theta, w.E and w.resd serve as scratch, all
+// free between the filter and the QR.
+static int kappa_of_block(Workspace& w, const z64* X, int64_t ldx, int64_t n, bool equilibrate, hipStream_t s,
+                          double* kappa) {
+  int st = kOk;
+  if (n <= 0) {
+    *kappa = std::nan("");
+    return kOk;
+  }
+  if (equilibrate) {
+    std::vector<double> g(n, 0.0);
+    CHASE_CHK(hipMemcpyAsync(w.theta, g.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    if ((st = residual_norms(X, ldx, X, ldx, w.theta, w.N, n, w.resd, s))) return st;  // ||x_j - 0 x_j||
+    CHASE_CHK(hipMemcpyAsync(g.data(), w.resd, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    CHASE_CHK(hipStreamSynchronize(s));
+    for (double& v : g) v = v > 0 ? 1.0 / v : 0.0;
+    CHASE_CHK(hipMemcpyAsync(w.theta, g.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    if ((st = scale_columns(X, ldx, w.theta, w.B, w.N, w.N, n, s))) return st;
+    CHASE_CHK(hipStreamSynchronize(s));  // g is read by the copy before it goes
+  } else if ((st = copy_columns(X, ldx, w.B, w.N, w.N, n, s))) {
+    return st;
+  }
+  rocblas_set_stream(w.rb, s);
+  rocblas_status r =
+      w.real ? rocsolver_dgesvd(w.rb, rocblas_svect_none, rocblas_svect_none, (rocblas_int)(2 * w.N),
+                                (rocblas_int)n, reinterpret_cast<double*>(w.B), (rocblas_int)(2 * w.N), w.theta,
+                                nullptr, 1, nullptr, 1, w.E, rocblas_inplace, w.info)
+             : rocsolver_zgesvd(w.rb, rocblas_svect_none, rocblas_svect_none, (rocblas_int)w.N, (rocblas_int)n,
+                                reinterpret_cast<rocblas_double_complex*>(w.B), (rocblas_int)w.N, w.theta, nullptr,
+                                1, nullptr, 1, w.E, rocblas_inplace, w.info);
+  if (r != rocblas_status_success) {
+    set_msg("rocsolver_zgesvd failed");
+    return kHipError;
+  }
+  std::vector<double> sv(n);
+  CHASE_CHK(hipMemcpyAsync(sv.data(), w.theta, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  CHASE_CHK(hipStreamSynchronize(s));
+  double lo = sv[0], hi = sv[0];
+  for (double v : sv) {
+    lo = std::min(lo, v);
+    hi = std::max(hi, v);
+  }
+  *kappa = lo > 0 ? hi / lo : std::numeric_limits<double>::infinity();
+  return kOk;
+}
+
 // State of one problem's ChASE loop (Alg. 2).  The single solve and the
 // batched solve drive the same steps; only the filter launch differs.
 struct ProblemState {
@@ -741,6 +864,9 @@ struct ProblemState {
   chase_stats_t S{};
   int64_t total_mv = 0;
   PhaseTimer t_lz, t_f, t_qr, t_rr;
+  int trace_level = 0;
+  std::vector<chase_trace_t>* trace = nullptr;
+  chase_trace_t rec{};  // the iteration being traced
 
   int init_timers() {
     int st;
@@ -779,6 +905,7 @@ struct ProblemState {
     mixed = P.precision != CHASE_FP64;
     std::memset(&S, 0, sizeof(S));
     if (!use_v0 && (st = fill_gaussian(V, ldv, N, ne, P.seed, s))) return st;
+    if (!use_v0 && (st = zero_pad_row(V, ldv, ne, s))) return st;
     if (P.bounds_given) {
       bnd[0] = P.b_sup;
       bnd[1] = P.mu_1;
@@ -789,6 +916,7 @@ struct ProblemState {
       int ns = nstarts;
       if (!starts) {
         if ((st = fill_gaussian(w->starts, N, N, 4, P.seed ^ 0x5DEECE66Dull, s))) return st;
+        if ((st = zero_pad_row(w->starts, N, 4, s))) return st;
         starts = w->starts;
         ld = N;
         ns = 4;
@@ -796,7 +924,7 @@ struct ProblemState {
       t_lz.start(s);
       if ((st = lanczos(*w, A, lda, starts, ld, ns, P.lanczos_steps, ne, bnd, s))) return st;
       t_lz.stop(s);
-      total_mv += (int64_t)ns * std::min<int64_t>(P.lanczos_steps, N);
+      total_mv += (int64_t)ns * std::min<int64_t>(P.lanczos_steps, w->real ? w->rows : N);
     }
     b_sup = bnd[0];
     mu1_cur = bnd[1];
@@ -843,6 +971,14 @@ struct ProblemState {
     return kOk;
   }
 
+  // Real problems: the padding row of an odd order (the last real row of
+  // the row-pair layout) is kept at zero.
+  int zero_pad_row(z64* X, int64_t ldx, int64_t n, hipStream_t s) {
+    if (!w->real || w->rows % 2 == 0) return kOk;
+    double* Xr = reinterpret_cast<double*>(X);
+    return dcopy_pad(Xr, 2 * ldx, w->rows, n, Xr, 2 * ldx, 2 * N, n, s);
+  }
+
   // active columns on rung r (contiguous: the sort puts higher rungs first)
   int n_rung(int r) const {
     int k = 0;
@@ -854,8 +990,11 @@ struct ProblemState {
   // FP64 filter GEMMs of this iteration (the columns not in FP32).
   std::vector<GemmArgs> plan() {
     const int nl = mixed ? n_low() : 0;
-    return plan_filter(A, lda, V + (int64_t)(locked + nl) * ldv, ldv, w->B + (int64_t)(locked + nl) * N, N, N,
-                       na() - nl, degs.data() + locked + nl, c, e, mu1_cur);
+    std::vector<GemmArgs> steps = plan_filter(A, lda, V + (int64_t)(locked + nl) * ldv, ldv,
+                                              w->B + (int64_t)(locked + nl) * N, N, N, na() - nl,
+                                              degs.data() + locked + nl, c, e, mu1_cur);
+    if (w->real) as_real_steps(steps);
+    return steps;
   }
 
   // Filter launched eagerly on `s` (single-problem solve).
@@ -906,6 +1045,12 @@ struct ProblemState {
       nl += nl32;
     }
     for (const GemmArgs& g : plan()) {
+      if (w->real) {
+        if ((st = dfilter_big_launch(g, s, w->tail_ws, w->tail_counters))) return st;
+        mv += g.N;
+        ++nl;
+        continue;
+      }
       int choice = kChoiceT0Tail;
       if (P.autotune && (st = tuned_choice(*w, g, s, &choice))) return st;
       if ((st = zgemm_nn_big_launch(g, s, true, w->tail_ws, w->tail_counters, choice))) return st;
@@ -925,6 +1070,22 @@ struct ProblemState {
     std::vector<double> Lam_est = Lam;
     if (it == 1) std::fill(Lam_est.begin(), Lam_est.end(), mu1_cur);
     const double cond = cond_est(Lam_est.data(), c, e, degs.data(), ne, locked);
+    const double acc0[3] = {t_f.acc, t_qr.acc, t_rr.acc};
+    if (trace_level > 0) {
+      rec = chase_trace_t{};
+      rec.iteration = it;
+      rec.locked = locked;
+      rec.n_active = na();
+      for (int j = locked; j < ne; ++j) rec.filter_matvecs += degs[j];
+      rec.kappa_est = cond;
+      rec.kappa_com = rec.kappa_com_active = rec.kappa_com_equil = std::nan("");
+      if (trace_level > 1) {
+        if ((st = kappa_of_block(*w, V, ldv, ne, false, s, &rec.kappa_com))) return st;
+        if ((st = kappa_of_block(*w, V + (int64_t)locked * ldv, ldv, na(), false, s, &rec.kappa_com_active)))
+          return st;
+        if ((st = kappa_of_block(*w, V, ldv, ne, true, s, &rec.kappa_com_equil))) return st;
+      }
+    }
     t_qr.start(s);
     int variant = 0;
     if ((st = caqr(*w, V, ldv, ne, cond, P.force_qr, &variant, s))) return st;
@@ -944,6 +1105,13 @@ struct ProblemState {
     CHASE_CHK(hipMemcpyAsync(rs_h.data(), w->resd, na() * sizeof(double), hipMemcpyDeviceToHost, s));
     CHASE_CHK(hipStreamSynchronize(s));
     collect_timers();
+    if (trace_level > 0 && trace && trace->size() < CHASE_TRACE_MAX) {
+      rec.qr_variant = variant;
+      rec.t_filter = t_f.acc - acc0[0];  // the filter's events are collected here
+      rec.t_qr = t_qr.acc - acc0[1];
+      rec.t_rr = t_rr.acc - acc0[2];
+      trace->push_back(rec);
+    }
     for (int j = 0; j < na(); ++j) {
       Lam[locked + j] = th_h[j];
       prev_resd[locked + j] = resd[locked + j];
@@ -1001,7 +1169,8 @@ struct ProblemState {
     S.iterations = it - 1;
     S.locked = locked;
     S.total_matvecs = total_mv;
-    S.filter_flops = 8.0 * (double)N * (double)N * (double)S.filter_matvecs;
+    S.filter_flops = w->real ? 2.0 * (double)w->rows * (double)w->rows * (double)S.filter_matvecs
+                             : 8.0 * (double)N * (double)N * (double)S.filter_matvecs;
     S.t_lanczos = t_lz.acc;
     S.t_filter += t_f.acc;
     S.t_qr = t_qr.acc;
@@ -1034,6 +1203,9 @@ using namespace chase;
 struct chase_handle_s {
   Workspace w;
   chase_params_t p;
+  bool real = false;  // created by chase_create_real
+  int trace_level = 0;
+  std::vector<chase_trace_t> trace;  // of the last solve
 };
 
 extern "C" {
@@ -1086,13 +1258,16 @@ int chase_destroy(chase_handle_t h) {
 int chase_solve(chase_handle_t h, const void* A_, int64_t lda, void* V_, int64_t ldv, int32_t use_v0,
                 const void* starts_, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
                 chase_stats_t* stats, chase_stream_t stream_) {
-  if (!h) return -1;
+  if (!h || h->real) return -1;
   int st = check_solve_args(h->w.N, A_, lda, V_, ldv, starts_, ld_starts, nstarts, ritzv, resid);
   if (st) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
   ProblemState ps;
   ps.w = &h->w;
   ps.P = h->p;
+  ps.trace_level = h->trace_level;
+  ps.trace = &h->trace;
+  h->trace.clear();
   ps.A = reinterpret_cast<const z64*>(A_);
   ps.lda = lda;
   ps.V = reinterpret_cast<z64*>(V_);
@@ -1125,6 +1300,156 @@ int chase_solve(chase_handle_t h, const void* A_, int64_t lda, void* V_, int64_t
   if (st) return st;
   if (stats) *stats = ps.S;
   return ps.S.status;
+}
+
+int chase_create_real(int64_t N, const chase_params_t* p, chase_handle_t* h) {
+  if (N < 2) return -1;
+  if (!valid_params(p) || (int64_t)p->nev + p->nex >= N || p->precision != CHASE_FP64) return -2;
+  if (!h) return -3;
+  auto* hh = new chase_handle_s();
+  hh->p = *p;
+  hh->real = true;
+  int st = hh->w.create_real(N, p->nev + p->nex);
+  if (st) {
+    delete hh;
+    *h = nullptr;
+    return st;
+  }
+  *h = hh;
+  return kOk;
+}
+
+int chase_solve_real(chase_handle_t h, const double* A, int64_t lda, double* V, int64_t ldv, int32_t use_v0,
+                     const double* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
+                     chase_stats_t* stats, chase_stream_t stream_) {
+  if (!h || !h->real) return -1;
+  Workspace& w = h->w;
+  const int64_t n_real = w.rows, np = w.N;  // order, row pairs
+  int st = check_solve_args(n_real, A, lda, V, ldv, starts, ld_starts, nstarts, ritzv, resid);
+  if (st) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+  const int ne = h->p.nev + h->p.nex;
+  // H in the row-pair layout: the caller's storage when the order and the
+  // leading dimension are even (and H 16-byte aligned), else a zero-padded copy
+  const z64* Apair = reinterpret_cast<const z64*>(A);
+  int64_t ldpair = lda / 2;
+  if (n_real % 2 != 0 || lda % 2 != 0) {
+    if ((st = w.ensure_hpad())) return st;
+    if ((st = dcopy_pad(A, lda, n_real, n_real, w.Hpad, 2 * np, 2 * np, 2 * np, s))) return st;
+    Apair = reinterpret_cast<const z64*>(w.Hpad);
+    ldpair = np;
+  }
+  w.Hr = A;
+  w.ldhr = lda;
+  // the block and the Lanczos starts in the row-pair layout
+  double* Cr = reinterpret_cast<double*>(w.Cint);
+  if (use_v0 && (st = dcopy_pad(V, ldv, n_real, ne, Cr, 2 * np, 2 * np, ne, s))) return st;
+  const z64* starts_pair = nullptr;
+  int64_t lds_pair = 0;
+  if (starts) {
+    if ((st = dcopy_pad(starts, ld_starts, n_real, nstarts, reinterpret_cast<double*>(w.lzW), 2 * np, 2 * np,
+                        nstarts, s)))
+      return st;
+    starts_pair = w.lzW;
+    lds_pair = np;
+  }
+  ProblemState ps;
+  ps.w = &w;
+  ps.P = h->p;
+  ps.trace_level = h->trace_level;
+  ps.trace = &h->trace;
+  h->trace.clear();
+  ps.A = Apair;
+  ps.lda = ldpair;
+  ps.V = w.Cint;
+  ps.ldv = np;
+  PhaseTimer t_all;
+  if ((st = t_all.init()) || (st = ps.init_timers())) {
+    t_all.destroy();
+    ps.destroy_timers();
+    return st;
+  }
+  auto run = [&]() -> int {
+    int r;
+    t_all.start(s);
+    if ((r = ps.setup(use_v0, starts_pair, lds_pair, nstarts, s))) return r;
+    while (ps.active()) {
+      if ((r = ps.prepare(s))) return r;
+      if ((r = ps.filter_eager(s))) return r;
+      if ((r = ps.post_filter(s))) return r;
+    }
+    if ((r = ps.finish(ritzv, resid, s))) return r;
+    if ((r = dcopy_pad(Cr, 2 * np, n_real, ne, V, ldv, n_real, ne, s))) return r;
+    t_all.stop(s);
+    CHASE_CHK(hipStreamSynchronize(s));
+    t_all.collect();
+    return kOk;
+  };
+  st = run();
+  ps.S.t_total = t_all.acc;
+  t_all.destroy();
+  ps.destroy_timers();
+  w.Hr = nullptr;
+  if (st) return st;
+  if (stats) *stats = ps.S;
+  return ps.S.status;
+}
+
+int chase_filter_real(const double* A, int64_t lda, double* V, int64_t ldv, double* W, int64_t ldw, int64_t N,
+                      int64_t n, const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs,
+                      chase_stream_t stream) {
+  if (!A || !aligned16(A)) return -1;
+  if (lda < N || lda % 2) return -2;
+  if (!V || !aligned16(V)) return -3;
+  if (ldv < N || ldv % 2) return -4;
+  if (!W || !aligned16(W)) return -5;
+  if (ldw < N || ldw % 2) return -6;
+  if (N < 2 || N % 2) return -7;
+  if (n < 0) return -8;
+  if (n > 0 && !degs) return -9;
+  for (int64_t j = 0; j < n; ++j)
+    if (degs[j] < 2 || degs[j] % 2 || (j > 0 && degs[j] < degs[j - 1])) return -9;
+  if (!(e > 0)) return -11;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  void* tws = nullptr;
+  int* tcnt = nullptr;
+  if (hipMalloc(&tws, (size_t)tail_workspace_bytes()) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&tcnt), sizeof(int) * kTailCounterInts) != hipSuccess) {
+    (void)hipGetLastError();
+    if (tws) (void)hipFree(tws);
+    return kAllocFailed;
+  }
+  int64_t mv = 0, nl = 0;
+  int st = tail_counters_init(tcnt, s);
+  if (!st)
+    st = run_filter(reinterpret_cast<const z64*>(A), lda / 2, reinterpret_cast<z64*>(V), ldv / 2,
+                    reinterpret_cast<z64*>(W), ldw / 2, N / 2, n, degs, c, e, mu_1, &mv, &nl, s, tws, tcnt, true);
+  hipError_t err = hipStreamSynchronize(s);
+  (void)hipFree(tws);
+  (void)hipFree(tcnt);
+  if (st) return st;
+  if (err != hipSuccess) {
+    set_last_error("chase_filter_real", err);
+    return kHipError;
+  }
+  if (matvecs) *matvecs = mv;
+  return kOk;
+}
+
+int chase_set_trace(chase_handle_t h, int32_t level) {
+  if (!h) return -1;
+  if (level < 0 || level > 2) return -2;
+  h->trace_level = level;
+  return kOk;
+}
+
+int chase_get_trace(chase_handle_t h, chase_trace_t* out, int32_t cap, int32_t* count) {
+  if (!h) return -1;
+  if (cap < 0 || (cap > 0 && !out)) return -3;
+  const int32_t n = std::min<int32_t>(cap, (int32_t)h->trace.size());
+  for (int32_t i = 0; i < n; ++i) out[i] = h->trace[(size_t)i];
+  if (count) *count = n;
+  return kOk;
 }
 
 int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As, const int64_t* ldas,

@@ -94,7 +94,10 @@ int grouped_grid(int cfg);
 // Split over K into `splits` partial products in `ws`, summed in fixed order;
 // hermitise = 1 stores (S + S^H)/2 (M == N); hermitise = 2 computes and
 // stores only the lower triangle of a Hermitian product (M == N), with a real
-// diagonal, leaving the strict upper triangle of Y untouched.
+// diagonal, leaving the strict upper triangle of Y untouched; hermitise = 3
+// does the same keeping only real parts (the product of two real blocks read
+// as complex row pairs: its real part is X^T Y, its imaginary part is not
+// part of the product).
 int zgemm_splitk(int opa, int opb, const GemmArgs& g, void* ws, int splits, int hermitise,
                  hipStream_t s);
 int64_t zgemm_splitk_workspace(int64_t M, int64_t N, int splits);
@@ -104,6 +107,13 @@ int choose_splits(int64_t M, int64_t N, int64_t K, int max_splits, bool lower = 
 // device), g.Y = G; g.lower_only computes only the tiles that hold an element
 // on or below the diagonal (M == N).  Allocates nothing.
 int zgrad_launch(const GemmArgs& g, hipStream_t s);
+
+// Real filter step (zfilter.hip): Y = alpha A B + beta Y + gamma Z for a real
+// matrix read as complex row pairs.  A: M x K complex view (2M real rows,
+// lda in complex units), B: real K x N block (double*, ldb in doubles, even),
+// Y, Z: complex views of real 2M x N blocks.  K and ldb even, A and B 16-byte
+// aligned; otherwise -1.  Same schedule and split-K tail as the FP64 step.
+int dfilter_big_launch(const GemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters);
 
 // Complex FP32 GEMM (mixed-precision filter): same contract with complex64 data.
 struct CGemmArgs {
@@ -171,6 +181,16 @@ int scale_columns(const z64* X, int64_t ldx, const double* g, z64* out, int64_t 
 int check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
 // Mirror the lower triangle into the upper one (Hermitian full storage).
 int hermitian_mirror_lower(z64* G, int64_t ld, int64_t n, hipStream_t s);
+// Real symmetric problems.  W[:, c] = H V[:, c] (c < nv <= 8) for real
+// symmetric H of order N; rows N .. rows_out - 1 of W are set to zero.
+int symv_block(const double* H, int64_t ldh, const double* V, int64_t ldv, double* W, int64_t ldw, int64_t N,
+               int64_t rows_out, int nv, hipStream_t s);
+// dst (rows_dst x cols_dst) = src (rows_src x cols_src) extended with zeros.
+int dcopy_pad(const double* src, int64_t lds, int64_t rows_src, int64_t cols_src, double* dst, int64_t ldd,
+              int64_t rows_dst, int64_t cols_dst, hipStream_t s);
+// R = Re(G) and G = R + 0 i for n x n blocks.
+int z_real_part(const z64* G, int64_t ldg, double* R, int64_t ldr, int64_t n, hipStream_t s);
+int d_to_z(const double* R, int64_t ldr, z64* G, int64_t ldg, int64_t n, hipStream_t s);
 // complex128 <-> complex64 conversions (column blocks).
 int convert_z_to_c(const z64* src, int64_t lds, c32* dst, int64_t ldd, int64_t N, int64_t n,
                    hipStream_t s);

@@ -406,6 +406,58 @@ __global__ __launch_bounds__(1024) void lanczos_step_kernel(zv* V, zv* Vold, zv*
   }
 }
 
+// ---- real symmetric problems ------------------------------------------------
+
+// W[:, c] = H V[:, c] (c < nv <= 8) for real symmetric H of order N: column m
+// of H is row m, so one wave per output row reads it coalesced.  Rows
+// N .. rows_out - 1 of W are written as zero (the padding row of the row-pair
+// layout).
+__global__ __launch_bounds__(256) void symv_kernel(const double* __restrict__ H, int64_t ldh,
+                                                   const double* __restrict__ V, int64_t ldv, double* W,
+                                                   int64_t ldw, int64_t N, int64_t rows_out, int nv) {
+  const int lane = threadIdx.x & 63;
+  const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= rows_out) return;  // whole waves
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (m < N) {
+    const double* col = H + m * ldh;
+    for (int64_t k = lane; k < N; k += 64) {
+      const double h = col[k];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < nv) acc[c] += h * V[k + c * ldv];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (c >= nv) break;
+    double x = acc[c];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) W[m + c * ldw] = x;
+  }
+}
+
+// dst (rows_dst x cols_dst) = src (rows_src x cols_src) zero-extended.
+__global__ void dcopy_pad_kernel(const double* src, int64_t lds, int64_t rows_src, int64_t cols_src, double* dst,
+                                 int64_t ldd, int64_t rows_dst) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (m >= rows_dst) return;
+  dst[m + j * ldd] = (m < rows_src && j < cols_src) ? src[m + j * lds] : 0.0;
+}
+
+// R = Re(G) and G = R + 0i for n x n blocks.
+__global__ void z_real_part_kernel(const zv* G, int64_t ldg, double* R, int64_t ldr, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i < n) R[i + j * ldr] = G[i + j * ldg].re;
+}
+__global__ void d_to_z_kernel(const double* R, int64_t ldr, zv* G, int64_t ldg, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i < n) G[i + j * ldg] = zv{R[i + j * ldr], 0.0};
+}
+
 // ---- counter-based Gaussian fill (splitmix64 + Box-Muller) ------------------
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -590,6 +642,41 @@ int hemv_block(const z64* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int
   }
   hipLaunchKernelGGL(hemv_kernel, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, reinterpret_cast<const zv*>(A), lda,
                      reinterpret_cast<const zv*>(V), ldv, reinterpret_cast<zv*>(W), ldw, N, nv);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int symv_block(const double* H, int64_t ldh, const double* V, int64_t ldv, double* W, int64_t ldw, int64_t N,
+               int64_t rows_out, int nv, hipStream_t s) {
+  if (nv < 1 || nv > 8 || rows_out < N) return -1;
+  if (rows_out <= 0) return kOk;
+  hipLaunchKernelGGL(symv_kernel, dim3((unsigned)cdiv(rows_out, 4)), dim3(256), 0, s, H, ldh, V, ldv, W, ldw, N,
+                     rows_out, nv);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int dcopy_pad(const double* src, int64_t lds, int64_t rows_src, int64_t cols_src, double* dst, int64_t ldd,
+              int64_t rows_dst, int64_t cols_dst, hipStream_t s) {
+  if (rows_dst <= 0 || cols_dst <= 0) return kOk;
+  hipLaunchKernelGGL(dcopy_pad_kernel, dim3((unsigned)cdiv(rows_dst, 256), (unsigned)cols_dst), dim3(256), 0, s,
+                     src, lds, rows_src, cols_src, dst, ldd, rows_dst);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int z_real_part(const z64* G, int64_t ldg, double* R, int64_t ldr, int64_t n, hipStream_t s) {
+  if (n <= 0) return kOk;
+  hipLaunchKernelGGL(z_real_part_kernel, dim3((unsigned)cdiv(n, 256), (unsigned)n), dim3(256), 0, s,
+                     reinterpret_cast<const zv*>(G), ldg, R, ldr, n);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int d_to_z(const double* R, int64_t ldr, z64* G, int64_t ldg, int64_t n, hipStream_t s) {
+  if (n <= 0) return kOk;
+  hipLaunchKernelGGL(d_to_z_kernel, dim3((unsigned)cdiv(n, 256), (unsigned)n), dim3(256), 0, s, R, ldr,
+                     reinterpret_cast<zv*>(G), ldg, n);
   CHASE_CHK_LAUNCH();
   return kOk;
 }

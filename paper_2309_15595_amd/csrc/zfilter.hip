@@ -343,11 +343,24 @@ constexpr int WGM = 2, WGN = 4, TM = 4, TN = 2;
 constexpr int A_BYTES = BK * BM * 16;
 constexpr int B_BYTES = BN * BK * 16;
 constexpr int STAGE = A_BYTES + B_BYTES;
+// real B operand (RB): 8 chunks of two consecutive k (16 bytes) per column
+constexpr int RB_COL = BK * 8;
 }  // namespace dz
 
 // Loads of K-tile [k0, k0 + 16) of tile (m0, n0) into `stage`: 64
-// instructions, 8 per wave.
-template <bool EDGE>
+// instructions, 8 per wave (48, 6 per wave, with a real B operand).
+//
+// RB: B is a real K x n block and A the complex view of a real matrix whose
+// row pairs (2 m', 2 m' + 1) are the real and imaginary parts of complex row
+// m' (the same memory).  Then complex row m' of A B holds rows 2 m' and
+// 2 m' + 1 of the real product, so the complex tile computes a real GEMM of
+// twice the rows with two real MFMA products per complex-by-real one, none of
+// them wasted.  The B tile is [n][chunk position] with 8 chunks of two
+// consecutive k (16 bytes) per column; chunk c of column n sits at position
+// c ^ ((n >> 1) & 7), so 16 consecutive columns reading the same chunk hit
+// 16 distinct pairs of banks.  One instruction moves 8 columns.  K and kend
+// must be even (a chunk never straddles kend).
+template <bool EDGE, bool RB>
 __device__ __forceinline__ void dz_issue(const GemmArgs& g, int64_t m0, int64_t n0, int64_t k0, int64_t kend,
                                          unsigned char* stage, int wave, int lane) {
   using namespace dz;
@@ -367,17 +380,34 @@ __device__ __forceinline__ void dz_issue(const GemmArgs& g, int64_t m0, int64_t 
       reinterpret_cast<zv*>(dst)[lane] = zv{0.0, 0.0};
     }
   }
+  if constexpr (RB) {
+    const double* Br = reinterpret_cast<const double*>(g.B);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int ib = wave * 4 + r;  // columns 4 ib .. 4 ib + 3
-    const int nl = ib * 4 + (lane >> 4);
-    const int kl = (lane & 15) ^ (nl & 15);
-    const int64_t n = n0 + nl, k = k0 + kl;
-    unsigned char* dst = stage + A_BYTES + ib * 1024;
-    if (kfull || k < kend) {
-      if (!EDGE || n < g.N) __builtin_amdgcn_global_load_lds(B + k + n * g.ldb, dst, 16, 0, 0);
-    } else {
-      reinterpret_cast<zv*>(dst)[lane] = zv{0.0, 0.0};
+    for (int r = 0; r < 2; ++r) {
+      const int ib = wave * 2 + r;  // columns 8 ib .. 8 ib + 7
+      const int nl = ib * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ ((nl >> 1) & 7);  // chunk stored at position lane & 7
+      const int64_t n = n0 + nl, k = k0 + 2 * c;
+      unsigned char* dst = stage + A_BYTES + ib * 1024;
+      if (kfull || k < kend) {
+        if (!EDGE || n < g.N) __builtin_amdgcn_global_load_lds(Br + k + n * g.ldb, dst, 16, 0, 0);
+      } else {
+        reinterpret_cast<zv*>(dst)[lane] = zv{0.0, 0.0};
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ib = wave * 4 + r;  // columns 4 ib .. 4 ib + 3
+      const int nl = ib * 4 + (lane >> 4);
+      const int kl = (lane & 15) ^ (nl & 15);
+      const int64_t n = n0 + nl, k = k0 + kl;
+      unsigned char* dst = stage + A_BYTES + ib * 1024;
+      if (kfull || k < kend) {
+        if (!EDGE || n < g.N) __builtin_amdgcn_global_load_lds(B + k + n * g.ldb, dst, 16, 0, 0);
+      } else {
+        reinterpret_cast<zv*>(dst)[lane] = zv{0.0, 0.0};
+      }
     }
   }
 }
@@ -389,7 +419,7 @@ __device__ __forceinline__ void dz_issue(const GemmArgs& g, int64_t m0, int64_t 
 // time) instead of one busy wave on two SIMDs (half of it); one with at most
 // 64 uses 4 x 2 waves of 32 x 32 (half a tile, with two busy waves per SIMD to
 // cover each other's LDS and barrier waits instead of one).
-template <bool EDGE, int LWGM, int LTM>
+template <bool EDGE, int LWGM, int LTM, bool RB>
 __device__ __forceinline__ void zdma_tile_impl(const GemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg, int64_t kend,
                                                zv* part, unsigned char* lds) {
   using dz::BM;
@@ -415,7 +445,7 @@ __device__ __forceinline__ void zdma_tile_impl(const GemmArgs& g, int64_t tm, in
       ci[a][b] = f64x4{0, 0, 0, 0};
     }
   const int64_t nkt = (kend - kbeg + BK - 1) / BK;
-  if (nkt > 0) dz_issue<EDGE>(g, m0, n0, kbeg, kend, lds, wave, lane);
+  if (nkt > 0) dz_issue<EDGE, RB>(g, m0, n0, kbeg, kend, lds, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int64_t kt = 0; kt < nkt; ++kt) {
@@ -426,8 +456,37 @@ __device__ __forceinline__ void zdma_tile_impl(const GemmArgs& g, int64_t tm, in
       // K-substep 0, the second before substep 2, so one wave's load issue
       // always overlaps the other's MFMAs
       if (ks == issue_at && kt + 1 < nkt)
-        dz_issue<EDGE>(g, m0, n0, kbeg + (kt + 1) * BK, kend, lds + ((kt + 1) & 1) * STAGE, wave, lane);
+        dz_issue<EDGE, RB>(g, m0, n0, kbeg + (kt + 1) * BK, kend, lds + ((kt + 1) & 1) * STAGE, wave, lane);
       if (!active) continue;
+      if constexpr (RB) {
+        // lane group kq takes k = 2 c + e, c = kq + 4 (ks / 2), e = ks % 2:
+        // each k of the tile once, the two halves of a chunk in consecutive
+        // substeps
+        const int c = kq + 4 * (ks >> 1), e = ks & 1;
+        const int kk = 2 * c + e;
+        double x[TN], ar[TM], ai[TM];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int n = wn * TN * 16 + j * 16 + l16;
+          x[j] = *reinterpret_cast<const double*>(cur + A_BYTES + n * dz::RB_COL + ((c ^ ((n >> 1) & 7)) << 4) +
+                                                  e * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int m = wm * TM * 16 + i * 16 + l16;
+          const zv v = *reinterpret_cast<const zv*>(cur + kk * (BM * 16) + (m << 4));
+          ar[i] = v.re;
+          ai[i] = v.im;
+        }
+#pragma unroll
+        for (int nb = 0; nb < TN; ++nb)
+#pragma unroll
+          for (int mb = 0; mb < TM; ++mb) {
+            cr[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[nb], ar[mb], cr[nb][mb], 0, 0, 0);
+            ci[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[nb], ai[mb], ci[nb][mb], 0, 0, 0);
+          }
+        continue;
+      }
       const int kk = ks * 4 + kq;
       double br[TN], bi[TN], ar[TM], ai[TM];
 #pragma unroll
@@ -503,20 +562,22 @@ __device__ __forceinline__ void zdma_tile_impl(const GemmArgs& g, int64_t tm, in
 }
 
 // One tile (or K range of one) in the layout its live region calls for.
+template <bool RB>
 __device__ __forceinline__ void zdma_tile(const GemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg, int64_t kend,
                                           zv* part, unsigned char* lds) {
   using namespace dz;
   if ((tm + 1) * BM <= g.M && (tn + 1) * BN <= g.N)
-    zdma_tile_impl<false, WGM, TM>(g, tm, tn, kbeg, kend, part, lds);
+    zdma_tile_impl<false, WGM, TM, RB>(g, tm, tn, kbeg, kend, part, lds);
   else if (g.N - tn * BN <= 32)
-    zdma_tile_impl<true, 8, 1>(g, tm, tn, kbeg, kend, part, lds);
+    zdma_tile_impl<true, 8, 1, RB>(g, tm, tn, kbeg, kend, part, lds);
   else if (g.N - tn * BN <= 64)
-    zdma_tile_impl<true, 4, 2>(g, tm, tn, kbeg, kend, part, lds);
+    zdma_tile_impl<true, 4, 2, RB>(g, tm, tn, kbeg, kend, part, lds);
   else
-    zdma_tile_impl<true, WGM, TM>(g, tm, tn, kbeg, kend, part, lds);
+    zdma_tile_impl<true, WGM, TM, RB>(g, tm, tn, kbeg, kend, part, lds);
 }
 
 // Whole launch of the direct-to-LDS step on the per-XCD work queue.
+template <bool RB>
 __device__ __forceinline__ void zdma_body(const GemmArgs& g, const TailSplit& tail) {
   using namespace dz;
   __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
@@ -526,7 +587,7 @@ __device__ __forceinline__ void zdma_body(const GemmArgs& g, const TailSplit& ta
   for (int64_t i; (i = queue_next(tail, q, &item)) >= 0;) {
     const WorkItem w = work_item(tail, o, i, g.K, BK);
     zv* part = w.seg < 0 ? nullptr : reinterpret_cast<zv*>(tail.ws) + w.seg * (int64_t)(BM * BN);
-    zdma_tile(g, w.tm, w.tn, w.kbeg, w.kend, part, lds);
+    zdma_tile<RB>(g, w.tm, w.tn, w.kbeg, w.kend, part, lds);
     if (w.seg >= 0) zbig_arrive<PF64, WGM, WGN, TM, TN, BK>(g, tail, w, &last);
   }
   queue_leave(tail);
@@ -774,7 +835,7 @@ __device__ __forceinline__ void zdma_grouped_body(const GroupEntry* __restrict__
     const GemmArgs g = row[p].g;
     int64_t tm, tn;
     tile_rc(tile_order(g.M, g.N, BM, BN), i - begin, &tm, &tn);
-    zdma_tile(g, tm, tn, 0, g.K, nullptr, lds);
+    zdma_tile<false>(g, tm, tn, 0, g.K, nullptr, lds);
   }
   queue_leave(t);
 }
@@ -790,12 +851,14 @@ __device__ __forceinline__ void zdma_grouped_body(const GroupEntry* __restrict__
 using C0 = Cfg<T0_ARGS>;
 using C1 = Cfg<T1_ARGS>;
 
-__global__ __launch_bounds__(dz::NT, 1) void zfilter_step(GemmArgs g, TailSplit t) { zdma_body(g, t); }
+__global__ __launch_bounds__(dz::NT, 1) void zfilter_step(GemmArgs g, TailSplit t) { zdma_body<false>(g, t); }
+// real symmetric H (row-pair view) times a real block
+__global__ __launch_bounds__(dz::NT, 1) void dfilter_step(GemmArgs g, TailSplit t) { zdma_body<true>(g, t); }
 __global__ __launch_bounds__(C1::NT, 2) void zfilter_step_n64(GemmArgs g, TailSplit t) {
   zbig_body<PF64, T1_ARGS>(g, t);
 }
 // Same schedule for the other large H-times-block products (Rayleigh-Ritz H C).
-__global__ __launch_bounds__(dz::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit t) { zdma_body(g, t); }
+__global__ __launch_bounds__(dz::NT, 1) void zgemm_nn_big(GemmArgs g, TailSplit t) { zdma_body<false>(g, t); }
 // FP32 filter step of the mixed-precision solve (complex64 H and X, FP32
 // accumulation): 128 x 128 tile, 8 waves of 64 x 32, K tile 16.
 #define TF32_ARGS 2, 4, 4, 2, 16
@@ -895,6 +958,27 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
     hipLaunchKernelGGL(zfilter_step_n64, dim3((unsigned)grid), dim3(C1::NT), 0, s, a, t);
   else
     hipLaunchKernelGGL(zfilter_step, dim3((unsigned)grid), dim3(dz::NT), 0, s, a, t);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int dfilter_big_launch(const GemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters) {
+  if (g.M <= 0 || g.N <= 0) return kOk;
+  if (g.ws != nullptr || g.upper_b || g.lower_only || g.bscale != nullptr) return -1;
+  if (!tail_ws || !tail_counters) return -1;
+  // 16-byte lanes: two k of a column of B, one complex row pair of A
+  if (g.K % 2 != 0 || g.ldb % 2 != 0 || reinterpret_cast<uintptr_t>(g.A) % 16 != 0 ||
+      reinterpret_cast<uintptr_t>(g.B) % 16 != 0)
+    return -1;
+  TileGeom geo;
+  geo.M = g.M; geo.N = g.N; geo.bm = kDma.bm; geo.bn = kDma.bn; geo.wgm = kDma.wgm; geo.wgn = kDma.wgn;
+  geo.narrow_cols = 32;
+  TailSplit t;
+  const int64_t grid = plan_schedule(geo, cdiv(g.K, kDma.bk), (int64_t)cu_count() * kDma.wg_per_cu, 16, true,
+                                     tail_ws, tail_counters, &t);
+  GemmArgs a = g;
+  if (a.K <= 0) a.alpha = 0.0;
+  hipLaunchKernelGGL(dfilter_step, dim3((unsigned)grid), dim3(dz::NT), 0, s, a, t);
   CHASE_CHK_LAUNCH();
   return kOk;
 }

@@ -239,14 +239,14 @@ __global__ void zsplitk_reduce(const zv* ws, int64_t stride, int splits, int64_t
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   int64_t m = idx % M, n = idx / M;
-  if (hermitise == 2 && m < n) return;  // lower triangle only
+  if (hermitise >= 2 && m < n) return;  // lower triangle only
   double sr = 0.0, si = 0.0;
   for (int s = 0; s < splits; ++s) {
     zv v = ws[s * stride + m + n * M];
     sr += v.re;
     si += v.im;
   }
-  if (hermitise == 2 && m == n) si = 0.0;  // real diagonal
+  if ((hermitise == 2 && m == n) || hermitise == 3) si = 0.0;  // real diagonal / real part
   if (hermitise == 1) {  // (S + S^H) / 2, M == N
     double tr = 0.0, ti = 0.0;
     for (int s = 0; s < splits; ++s) {
@@ -320,7 +320,7 @@ int zgemm_splitk(int opa, int opb, const GemmArgs& g_in, void* ws, int splits, i
   g.ws = reinterpret_cast<z64*>(ws);
   g.ws_stride = g.M * g.N;
   g.k_chunk = kchunk;
-  if (hermitise == 2) g.lower_only = 1;  // tiles wholly above the diagonal are never read
+  if (hermitise >= 2) g.lower_only = 1;  // tiles wholly above the diagonal are never read
   const int64_t tiles = cdiv(g.M, BM) * cdiv(g.N, BN);
   dim3 blocks((unsigned)(8 * cdiv(tiles, 8)), (unsigned)splits, 1);
   if (opa == 1 && opb == 0) {

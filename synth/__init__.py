@@ -12,6 +12,8 @@ from .problems import (  # noqa: F401
     gaussian_unitary,
     hermitian_from_spectrum,
     make_problem,
+    real_gaussian,
+    symmetric_from_spectrum,
     uniform_spectrum,
     CFG_PARITY,
 )

@@ -102,6 +102,43 @@ def hermitian_from_spectrum(lam: np.ndarray, basis: str = "gaussian",
     return _hermitise_np(A)
 
 
+def real_gaussian(rng: np.random.Generator, shape) -> np.ndarray:
+    """Standard normal float64 entries."""
+    return rng.standard_normal(shape)
+
+
+def symmetric_from_spectrum(lam: np.ndarray, seed: int = SEED_Q) -> np.ndarray:
+    """Dense real symmetric A = Q diag(lam) Q^T, Q the orthogonal factor of
+    numpy's QR of a seeded real Gaussian matrix (float64, C order)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    N = lam.shape[0]
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((N, N)))
+    A = (Q * lam[None, :]) @ Q.T
+    return 0.5 * (A + A.T)
+
+
+def symmetric_from_spectrum_torch(lam: np.ndarray, seed: int = SEED_Q, device="cuda"):
+    """Dense real symmetric matrix with eigenvalues ``lam`` built on a torch
+    device: Q = C^T diag(s) C with C the orthonormal DCT-II matrix and s
+    seeded random signs (dense and orthogonal; three N^3 products).  Returns
+    a (N, N) float64 tensor, symmetric, so row- and column-major agree."""
+    import torch
+
+    lam = np.asarray(lam, dtype=np.float64)
+    N = lam.shape[0]
+    s = torch.from_numpy(np.where(np.random.default_rng(seed).random(N) < 0.5, -1.0, 1.0)).to(device)
+    k = torch.arange(N, dtype=torch.float64, device=device)
+    C = torch.cos(torch.pi * (2.0 * k[None, :] + 1.0) * k[:, None] / (2.0 * N)) * (2.0 / N) ** 0.5
+    C[0] *= 0.5 ** 0.5
+    B = (C.T * torch.from_numpy(lam).to(device)[None, :]) @ C      # C^T diag(lam) C
+    B *= s[:, None] * s[None, :]                                   # S (.) S
+    A = C.T @ (B @ C)                                              # C^T (.) C
+    del B, C
+    A += A.T.clone()
+    A *= 0.5
+    return A
+
+
 def _circulant_first_column(lam: np.ndarray) -> np.ndarray:
     # With the unitary DFT F (F_jk = exp(-2 pi i j k / N) / sqrt(N)),
     # F diag(lam) F^H is circulant: entry (j, k) is fft(lam)[(j - k) mod N] / N.
@@ -189,7 +226,18 @@ def make_problem(N: int, nev: int, nex: int, spectrum: str = "uniform",
                  seed_v0: int = SEED_V0, seed_lanczos: int = SEED_LANCZOS,
                  n_starts: int = 4, build_matrix: bool = True,
                  name: Optional[str] = None, deg: int = 20,
-                 tol: float = 1e-10) -> Problem:
+                 tol: float = 1e-10, real: bool = False) -> Problem:
+    """real=True: a real symmetric matrix (Gaussian orthogonal rotation) with
+    real Gaussian initial block and Lanczos starts."""
+    if real:
+        if spectrum not in ("uniform", "dft"):
+            raise ValueError(f"unknown spectrum {spectrum!r}")
+        lam = uniform_spectrum(N) if spectrum == "uniform" else dft_like_spectrum(N)
+        A = symmetric_from_spectrum(lam, seed=seed) if build_matrix else None
+        V0 = real_gaussian(np.random.default_rng(seed_v0), (N, nev + nex))
+        starts = real_gaussian(np.random.default_rng(seed_lanczos), (N, n_starts))
+        return Problem(name=name or f"{spectrum}-real-N{N}", N=N, nev=nev, nex=nex,
+                       lam=lam, A=A, V0=V0, starts=starts, deg=deg, tol=tol)
     if spectrum == "uniform":
         lam = uniform_spectrum(N)
     elif spectrum == "dft":

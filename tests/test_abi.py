@@ -87,6 +87,11 @@ def test_invalid_arguments_rejected_on_host():
     bad = L.default_params(nev=10, nex=5, deg=3)
     assert lib.chase_create(100, ctypes.byref(bad), ctypes.byref(h)) == -2
     assert lib.chase_eigval_grad(10, 0, None, 10, None, None, 10, 0, None) == -2
+    assert lib.chase_solve_real(None, None, 0, None, 0, 1, None, 0, 0, None, None, None, None) == -1
+    assert lib.chase_filter_real(None, 2, None, 2, None, 2, 2, 1, None, 0.0, 1.0, -1.5, None, None) == -1
+    assert lib.chase_create_real(1, None, None) == -1
+    assert lib.chase_set_trace(None, 1) == -1
+    assert lib.chase_get_trace(None, None, 0, None) == -1
     assert lib.chase_filter(None, 10, None, 10, None, 10, 10, 1, None, 0.0, 1.0, -1.0, None, None) == -1
     assert np.isnan(L.chase_cond_est([1.0], 0.0, 0.0, [2], 0))
 
@@ -102,9 +107,11 @@ def test_struct_sizes_match_c_compiler(tmp_path):
         pytest.skip("no host C compiler")
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "chase_hip.h"\n'
-                   'int main(void){printf("%zu %zu\\n", sizeof(chase_params_t), sizeof(chase_stats_t));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu\\n", sizeof(chase_params_t), sizeof(chase_stats_t),'
+                   ' sizeof(chase_trace_t));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     assert int(out[0]) == ctypes.sizeof(L.chase_params_t)
     assert int(out[1]) == ctypes.sizeof(L.chase_stats_t)
+    assert int(out[2]) == ctypes.sizeof(L.chase_trace_t)

@@ -232,6 +232,124 @@ def test_solve_forced_qr_variants(L, force):
     assert info.stats["qr_count"][force] == info.stats["iterations"]
 
 
+def _kappa(X):
+    s = np.linalg.svd(X, compute_uv=False)
+    return s[0] / s[-1]
+
+
+def _oracle_condition_record(p, **params):
+    """Per iteration of the oracle's solve: the estimate and kappa_2 of the
+    block 1D-CAQR receives, of its filtered columns, and of the block with
+    unit columns."""
+    rec = []
+    orig = oc.caqr
+
+    def spy(X, cond, force=None):
+        rec.append((cond, X.copy()))
+        return orig(X, cond, force)
+
+    try:
+        oc.caqr = spy
+        r = oc.chase(p.A, oc.Params(nev=p.nev, nex=p.nex, **params), V0=p.V0, starts=p.starts)
+    finally:
+        oc.caqr = orig
+    out = []
+    for h, (est, X) in zip(r.history, rec):
+        lk = h["locked_before"]
+        out.append(dict(est=est, whole=_kappa(X), active=_kappa(X[:, lk:]),
+                        equil=_kappa(X / np.linalg.norm(X, axis=0))))
+    return r, out
+
+
+@pytest.mark.parametrize("opt", [1, 0])
+def test_trace_condition_numbers(L, parity_problem, opt):
+    """The per-iteration trace: the estimate of Alg. 5 and exact condition
+    numbers of the block 1D-CAQR factors (Sec. 4.2's comparison), against the
+    oracle iteration by iteration; the estimate bounds kappa_2 of the filtered
+    columns from the second iteration on."""
+    from paper_2309_15595_amd.api import Solver
+    p = parity_problem
+    r, orc = _oracle_condition_record(p, opt=opt)
+    with Solver(p.N, p.nev, p.nex, opt=opt) as s:
+        s.set_trace(2)
+        ritz, resid, info = s.solve_colmajor(cm(p.A), cm(p.V0), True, cm(p.starts))
+        tr = s.trace()
+    assert info.converged
+    st = info.stats
+    assert len(tr) == st["iterations"]
+    assert [t["iteration"] for t in tr] == list(range(1, len(tr) + 1))
+    assert sum(t["filter_matvecs"] for t in tr) == st["filter_matvecs"]
+    assert sum(t["t_filter"] for t in tr) == pytest.approx(st["t_filter"], rel=1e-9)
+    assert sum(t["t_qr"] for t in tr) == pytest.approx(st["t_qr"], rel=1e-9)
+    for t in tr:
+        assert t["n_active"] == p.nev + p.nex - t["locked"]
+    print()
+    for i, t in enumerate(tr):
+        o = orc[i] if i < len(orc) else None
+        print(f"it {t['iteration']:2d} locked {t['locked']:3d} est {t['kappa_est']:.4e} "
+              f"whole {t['kappa_com']:.4e} active {t['kappa_com_active']:.4e} "
+              f"equil {t['kappa_com_equil']:.4e} qr {t['qr_variant']}"
+              + (f" | oracle est {o['est']:.4e} whole {o['whole']:.4e} active {o['active']:.4e} "
+                 f"equil {o['equil']:.4e}" if o else ""))
+    # Alg. 5 takes kappa_2 of the filter's input as 1; the first input here is
+    # Gaussian, not orthonormal
+    k0 = _kappa(p.V0)
+    assert tr[0]["kappa_com"] <= tr[0]["kappa_est"] * k0
+    for t in tr[1:]:
+        assert t["kappa_est"] >= t["kappa_com_active"] * (1 - 1e-8), t
+        if t["locked"] == 0:
+            assert t["kappa_est"] >= t["kappa_com"] * (1 - 1e-8), t
+    # the same iterations as the oracle while the locking agrees: the estimate
+    # is a closed form of the Ritz values and bounds, the kappa_2 figures SVDs
+    # of blocks equal to ~1e-11; the branch of Alg. 4 follows
+    same = 0
+    for i, t in enumerate(tr):
+        if i >= len(r.history) or r.history[i]["locked_before"] != t["locked"]:
+            break
+        o = orc[i]
+        assert t["kappa_est"] == pytest.approx(o["est"], rel=1e-7)
+        assert t["kappa_com"] == pytest.approx(o["whole"], rel=1e-6)
+        assert t["kappa_com_active"] == pytest.approx(o["active"], rel=1e-6)
+        assert t["kappa_com_equil"] == pytest.approx(o["equil"], rel=1e-6)
+        assert t["qr_variant"] == r.history[i]["qr"]
+        same += 1
+    assert same >= min(len(tr), len(r.history)) - 1
+
+
+def test_trace_levels(L):
+    from paper_2309_15595_amd.api import Solver
+    p = synth.make_problem(300, 12, 6, seed=9)
+    with Solver(p.N, p.nev, p.nex) as s:
+        s.solve_colmajor(cm(p.A), cm(p.V0), True, cm(p.starts))
+        assert s.trace() == []                      # off by default
+        s.set_trace(1)
+        _, _, info = s.solve_colmajor(cm(p.A), cm(p.V0), True, cm(p.starts))
+        tr = s.trace()
+        assert len(tr) == info.stats["iterations"]
+        assert all(np.isnan(t["kappa_com"]) and np.isnan(t["kappa_com_equil"]) for t in tr)  # no SVD
+        assert all(t["kappa_est"] > 0 for t in tr)
+        s.set_trace(1)
+        _, _, info2 = s.solve_colmajor(cm(p.A), cm(p.V0), True, cm(p.starts))
+        assert len(s.trace()) == info2.stats["iterations"]  # cleared per solve
+        with pytest.raises(ValueError):
+            s.set_trace(3)
+
+
+def test_householder_same_path_as_cholesky(L, parity_problem, parity_oracle):
+    """Forcing Householder QR leaves the iteration count and the MatVecs
+    unchanged (Sec. 4.3's comparison of QR variants)."""
+    p = parity_problem
+    ritz_a, _, _, info_a = solve_gpu(p)
+    ritz_h, resid_h, X_h, info_h = solve_gpu(p, force_qr=3)
+    assert info_h.converged
+    check_solution(p, ritz_h, resid_h, X_h)
+    assert info_h.stats["iterations"] == info_a.stats["iterations"]
+    assert abs(info_h.stats["filter_matvecs"] - info_a.stats["filter_matvecs"]) <= \
+        0.01 * info_a.stats["filter_matvecs"]
+    assert np.max(np.abs(ritz_h - ritz_a)) <= 1e-12 * p.norm2
+    assert info_h.stats["qr_count"][3] == info_h.stats["iterations"]
+
+
 def test_solve_not_converged_status(L, parity_problem):
     ritz, resid, X, info = solve_gpu(parity_problem, max_iter=1)
     assert info.status == 1 and not info.converged
