@@ -13,8 +13,8 @@ Printed: one JSON line.  value = Chebyshev-filter TFLOP/s in FP64
 (algorithmic 8 N^2 per MatVec over the filter-phase time measured with HIP
 events on the solve's stream); ms_per_step = time to solution.  The same
 line carries the filter kernel's roofline position, the mixed-precision
-(FP32 filter + FP64 refinement) solve on the same problem, the real symmetric
-FP64 solve of the same spectrum, full-size checks against the prescribed
+(FP32 filter + FP64 refinement) solve on the same problem, the complex64 and
+real symmetric FP64 variants, full-size checks against the prescribed
 spectrum and the CPU oracle's rate on a bounded sample.
 """
 from __future__ import annotations
@@ -46,6 +46,7 @@ def parse_args():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-real", action="store_true", help="skip the real symmetric solve")
+    ap.add_argument("--no-c64", action="store_true", help="skip the complex64 solve")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -213,6 +214,35 @@ def main():
                 "iterations": mst["iterations"]}
             log(args, f"mixed {name}: {mst['t_total']:.2f} s")
 
+    if not args.no_c64:
+        # the complex64 variant on the same matrix rounded to complex64, at a
+        # tolerance its FP32 products reach (about sqrt(N) u_32 ||H||)
+        c64_tol = 2e-5
+        A32 = A.to(torch.complex64)
+        V32_0 = V0.to(torch.complex64)
+        S32 = S.to(torch.complex64)
+        V32 = torch.empty_like(V32_0)
+        with Solver(N, nev, nex, dtype=torch.complex64, deg=20, max_deg=36, opt=1, tol=c64_tol) as cs:
+            cruns = []
+            for i in range(1 + 1):   # one warm-up, one timed
+                V32.copy_(V32_0)
+                cruns.append(cs.solve_colmajor(A32, V32, True, S32))
+        critz, cresid, cinfo = cruns[-1]
+        cst = cinfo.stats
+        out["c64"] = {
+            "workload": f"complex64 H (the same matrix rounded), tol {c64_tol:g}",
+            "time_to_solution_s": cst["t_total"],
+            "filter_tflops_fp32": cst["filter_flops"] / cst["t_filter"] / 1e12,
+            "filter_frac_of_fp32_peak": cst["filter_flops"] / cst["t_filter"] / 1e12 / PEAK["f32"],
+            "phases_s": {k: cst[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr")},
+            "iterations": cst["iterations"], "filter_matvecs": cst["filter_matvecs"],
+            "converged": bool(cinfo.converged),
+            "max_abs_eig_err_over_normA": float(np.max(np.abs(critz - lam[:nev])) / normA),
+            "max_resid_over_normA": float(np.max(cresid) / normA)}
+        log(args, f"c64: {cst['t_total']:.2f} s, filter {out['c64']['filter_tflops_fp32']:.1f} TFLOP/s")
+        del A32, V32_0, S32, V32
+        torch.cuda.empty_cache()
+
     if not args.no_real:
         # the real symmetric variant on the same spectrum (2 N^2 flops per MatVec)
         torch.cuda.empty_cache()
@@ -222,7 +252,7 @@ def main():
         Sr = torch.from_numpy(np.ascontiguousarray(
             synth.real_gaussian(np.random.default_rng(sp.SEED_LANCZOS), (N, 4)).T)).to(dev)
         Vr = torch.empty_like(Vr0)
-        with Solver(N, nev, nex, real=True, deg=20, max_deg=36, opt=1, tol=1e-10) as rs:
+        with Solver(N, nev, nex, dtype=torch.float64, deg=20, max_deg=36, opt=1, tol=1e-10) as rs:
             rruns = []
             for i in range(1 + 1):   # one warm-up, one timed
                 Vr.copy_(Vr0)
@@ -236,6 +266,8 @@ def main():
             "filter_tflops": rst["filter_flops"] / rst["t_filter"] / 1e12,
             "filter_frac_of_fp64_peak": rst["filter_flops"] / rst["t_filter"] / 1e12 / PEAK["f64"],
             "phases_s": {k: rst[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr")},
+            "filter_launches": rst["filter_launches"],
+            "avg_launch_ms": rst["t_filter"] / max(1, rst["filter_launches"]) * 1e3,
             "iterations": rst["iterations"], "filter_matvecs": rst["filter_matvecs"],
             "converged": bool(rinfo.converged),
             "max_abs_eig_err_over_normA": float(np.max(np.abs(rritz - lam[:nev])) / normA),

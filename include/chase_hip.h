@@ -120,7 +120,7 @@ int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h);
  *   stats  (host, nullable) */
 int chase_solve(chase_handle_t h, const void* A, int64_t lda, void* V, int64_t ldv, int32_t use_v0,
                 const void* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
-                chase_stats_t* stats, chase_stream_t stream);  /* -1: null or real handle */
+                chase_stats_t* stats, chase_stream_t stream);  /* -1: null, real or complex64 handle */
 
 int chase_destroy(chase_handle_t h);
 
@@ -176,6 +176,21 @@ int chase_solve_real(chase_handle_t h, const double* A, int64_t lda, double* V, 
 int chase_filter_real(const double* A, int64_t lda, double* V, int64_t ldv, double* W, int64_t ldw, int64_t N,
                       int64_t n, const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs,
                       chase_stream_t stream);
+
+/* ---- complex64 H (the library's single-precision complex variant) --------
+ * A, V and starts are complex64 ((re, im) float pairs, device, 16-byte
+ * aligned).  H is used in place (8 N^2 bytes, no copy): the filter and the
+ * Rayleigh-Ritz product H Q run on the FP32 matrix kernels; QR, the small
+ * eigensolve, residuals and locking run in FP64 on an internal complex128
+ * copy of the block, which is rounded back to complex64 in V at the end.
+ * The attainable residual is set by the FP32 products, about sqrt(N) u_32
+ * ||H||: choose tol accordingly (1e-5 at N = 20000).  params.precision must
+ * not be CHASE_BF16X3_MIXED; it is otherwise not used. */
+int chase_create_c64(int64_t N, const chase_params_t* p, chase_handle_t* h);
+/* chase_solve for complex64 data; -1 for a handle not made by chase_create_c64. */
+int chase_solve_c64(chase_handle_t h, const void* A, int64_t lda, void* V, int64_t ldv, int32_t use_v0,
+                    const void* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
+                    chase_stats_t* stats, chase_stream_t stream);
 
 /* ---- steps of the loop, exposed for element-wise checks ------------------
  * These run one step of Alg. 2 exactly as chase_solve does. */

@@ -93,6 +93,9 @@ SIGNATURES = {
                                    C.POINTER(chase_stats_t), _P]),
     "chase_filter_real": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D,
                                     _I64P, _P]),
+    "chase_create_c64": (C.c_int, [_I64, C.POINTER(chase_params_t), C.POINTER(_P)]),
+    "chase_solve_c64": (C.c_int, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _I32, _DP, _DP,
+                                  C.POINTER(chase_stats_t), _P]),
     "chase_set_trace": (C.c_int, [_P, _I32]),
     "chase_get_trace": (C.c_int, [_P, C.POINTER(chase_trace_t), _I32, _I32P]),
     "chase_status_string": (C.c_char_p, [C.c_int]),
@@ -180,6 +183,22 @@ def chase_solve_real(h, A_ptr, lda, V_ptr, ldv, use_v0, starts_ptr, ld_starts, n
     st = load().chase_solve_real(h, A_ptr, lda, V_ptr, ldv, use_v0, starts_ptr or None, ld_starts,
                                  nstarts, ritz, resid, C.byref(stats), stream)
     check(st, "chase_solve_real", allow_not_converged=True)
+    return list(ritz), list(resid), stats
+
+
+def chase_create_c64(N: int, params: chase_params_t):
+    h = _P()
+    check(load().chase_create_c64(N, C.byref(params), C.byref(h)), "chase_create_c64")
+    return h
+
+
+def chase_solve_c64(h, A_ptr, lda, V_ptr, ldv, use_v0, starts_ptr, ld_starts, nstarts, nev, stream):
+    ritz = f64_array(nev)
+    resid = f64_array(nev)
+    stats = chase_stats_t()
+    st = load().chase_solve_c64(h, A_ptr, lda, V_ptr, ldv, use_v0, starts_ptr or None, ld_starts,
+                                nstarts, ritz, resid, C.byref(stats), stream)
+    check(st, "chase_solve_c64", allow_not_converged=True)
     return list(ritz), list(resid), stats
 
 

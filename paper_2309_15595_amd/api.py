@@ -44,11 +44,19 @@ class SolveInfo:
 class Solver:
     """A chase_create/chase_destroy handle for problems of order N."""
 
-    def __init__(self, N: int, nev: int, nex: int, *, real: bool = False, **params):
-        """real=True: a real symmetric problem (float64 data, chase_create_real)."""
-        self.N, self.nev, self.nex, self.real = N, nev, nex, real
+    _KINDS = {torch.complex128: (_lib.chase_create, _lib.chase_solve),
+              torch.float64: (_lib.chase_create_real, _lib.chase_solve_real),
+              torch.complex64: (_lib.chase_create_c64, _lib.chase_solve_c64)}
+
+    def __init__(self, N: int, nev: int, nex: int, *, dtype=torch.complex128, **params):
+        """dtype: complex128 (Hermitian), float64 (real symmetric,
+        chase_create_real) or complex64 (chase_create_c64)."""
+        if dtype not in self._KINDS:
+            raise TypeError(f"unsupported dtype {dtype}")
+        self.N, self.nev, self.nex, self.dtype = N, nev, nex, dtype
         self.params = _lib.default_params(nev=nev, nex=nex, **params)
-        self.h = (_lib.chase_create_real if real else _lib.chase_create)(N, self.params)
+        create, self._solve = self._KINDS[dtype]
+        self.h = create(N, self.params)
 
     def close(self):
         if self.h is not None:
@@ -86,14 +94,13 @@ class Solver:
         """A_cm: (N, N) tensor holding A column-major; V_cm: (n_e, N) tensor
         holding the N x n_e block column-major (in/out)."""
         N = self.N
-        dt = torch.float64 if self.real else torch.complex128
+        dt = self.dtype
         _check_dev(A_cm, (N, N), dt)
         _check_dev(V_cm, (self.nev + self.nex, N), dt)
         ns = 0 if starts_cm is None else starts_cm.shape[0]
         if starts_cm is not None:
             _check_dev(starts_cm, (ns, N), dt)
-        solve = _lib.chase_solve_real if self.real else _lib.chase_solve
-        ritz, resid, stats = solve(
+        ritz, resid, stats = self._solve(
             self.h, _lib.dptr(A_cm), N, _lib.dptr(V_cm), N, int(use_v0), _lib.dptr(starts_cm),
             N, ns, self.nev, _lib.stream_ptr(stream))
         return np.array(ritz), np.array(resid), SolveInfo(stats.status == 0, stats.status,
@@ -147,7 +154,7 @@ def eigsh(A: torch.Tensor, nev: int, nex: int, *, deg: int = 20, tol: float = 1e
         if precision != "fp64":
             raise ValueError("the real symmetric path is FP64 only")
         _check_dev(A, (N, N), torch.float64)
-        with Solver(N, nev, nex, real=True, deg=deg, tol=tol, opt=int(opt), max_deg=max_deg,
+        with Solver(N, nev, nex, dtype=torch.float64, deg=deg, tol=tol, opt=int(opt), max_deg=max_deg,
                     max_iter=max_iter, seed=seed) as s:
             # symmetric: the row-major memory is the column-major matrix
             if V0 is not None:

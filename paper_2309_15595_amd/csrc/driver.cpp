@@ -233,6 +233,12 @@ struct Workspace {
   double* Hpad = nullptr;      // 2N x 2N copy of H when its own layout does not fit
   const double* Hr = nullptr;  // this solve's H (real, order rows) for the Lanczos products
   int64_t ldhr = 0;
+  // complex64 problems: H stays in the caller's complex64 storage; the filter
+  // and the Rayleigh-Ritz H Q run on the FP32 kernels, the rest in FP64 on an
+  // internal complex128 copy of the block (Cint).
+  bool c64 = false;
+  const c32* H32 = nullptr;    // this solve's H
+  int64_t ldh32 = 0;
   rocblas_handle rb = nullptr;
   std::vector<void*> owned;
 
@@ -306,6 +312,18 @@ struct Workspace {
     rows = n_real;
     st = st ? st : alloc(&Gr, (size_t)ne_ * ne_);
     st = st ? st : alloc(&Cint, (size_t)N * ne_);
+    if (st) release();
+    return st;
+  }
+  // Workspace of a complex64 problem: FP32 ping-pong blocks, no copy of H.
+  int create_c64(int64_t n, int ne_) {
+    int st = create(n, ne_, false, true, false);
+    if (st) return st;
+    c64 = true;
+    const size_t nne = (size_t)N * ne_;
+    st = st ? st : alloc(&X32a, nne);
+    st = st ? st : alloc(&X32b, nne);
+    st = st ? st : alloc(&Cint, nne);
     if (st) release();
     return st;
   }
@@ -656,7 +674,18 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   g.B = Q; g.ldb = ldq;
   g.Y = w.B; g.ldy = N;
   int st;
-  if (w.real) {
+  if (w.c64) {  // H Q in FP32 from the complex64 H, back to FP64
+    if ((st = convert_z_to_c(Q, ldq, w.X32a, N, N, n, s))) return st;
+    CGemmArgs c;
+    c.M = N; c.N = n; c.K = N;
+    c.A = w.H32; c.lda = w.ldh32;
+    c.B = w.X32a; c.ldb = N;
+    c.Y = w.X32b; c.ldy = N;
+    c.Z = w.X32b; c.ldz = N;
+    c.alpha = 1.0f; c.beta = 0.0f; c.gamma = 0.0f;
+    if ((st = cfilter_big_launch(c, s, w.tail_ws, w.tail_counters))) return st;
+    st = convert_c_to_z(w.X32b, N, w.B, N, N, n, s);
+  } else if (w.real) {
     g.K = 2 * N;
     g.ldb = 2 * ldq;
     st = dfilter_big_launch(g, s, w.tail_ws, w.tail_counters);
@@ -721,6 +750,8 @@ static int lanczos(Workspace& w, const z64* A, int64_t lda, const z64* starts, i
     if (w.real)
       st = symv_block(w.Hr, w.ldhr, reinterpret_cast<const double*>(w.lzV), 2 * N, reinterpret_cast<double*>(w.lzW),
                       2 * N, w.rows, 2 * N, nstarts, s);
+    else if (w.c64)
+      st = hemv_block_c64(w.H32, w.ldh32, w.lzV, N, w.lzW, N, N, nstarts, s);
     else
       st = hemv_block(A, lda, w.lzV, N, w.lzW, N, N, nstarts, s);
     if (st) return st;
@@ -867,6 +898,8 @@ struct ProblemState {
   int trace_level = 0;
   std::vector<chase_trace_t>* trace = nullptr;
   chase_trace_t rec{};  // the iteration being traced
+  const c32* A32 = nullptr;  // H for the FP32 rung: the library's copy, or a complex64 caller's own
+  int64_t lda32 = 0;
 
   int init_timers() {
     int st;
@@ -902,7 +935,7 @@ struct ProblemState {
     N = w->N;
     nev = P.nev;
     ne = P.nev + P.nex;
-    mixed = P.precision != CHASE_FP64;
+    mixed = P.precision != CHASE_FP64 || w->c64;
     std::memset(&S, 0, sizeof(S));
     if (!use_v0 && (st = fill_gaussian(V, ldv, N, ne, P.seed, s))) return st;
     if (!use_v0 && (st = zero_pad_row(V, ldv, ne, s))) return st;
@@ -934,13 +967,20 @@ struct ProblemState {
     sw16_abs = P.bf16_switch * bnd[3];
     c = 0.5 * (b_sup + mu_ne);
     e = 0.5 * (b_sup - mu_ne);
-    if (mixed && (st = convert_z_to_c(A, lda, w->A32, N, N, N, s))) return st;
+    if (w->c64) {
+      A32 = w->H32;
+      lda32 = w->ldh32;
+    } else if (mixed) {
+      A32 = w->A32;
+      lda32 = N;
+      if ((st = convert_z_to_c(A, lda, w->A32, N, N, N, s))) return st;
+    }
     if (P.precision == CHASE_BF16X3_MIXED && (st = bsplit_planes(A, lda, N, w->P16, s))) return st;
     degs.assign(ne, P.deg);
     Lam.assign(ne, 0.0);
     resd.assign(ne, std::numeric_limits<double>::infinity());
     prev_resd = resd;
-    low.assign(ne, (char)P.precision);
+    low.assign(ne, w->c64 ? (char)1 : (char)P.precision);  // complex64: every column on the FP32 rung
     th_h.assign(ne, 0.0);
     rs_h.assign(ne, 0.0);
     return copy_columns(V, ldv, w->C2, N, N, ne, s);
@@ -1028,13 +1068,14 @@ struct ProblemState {
     }
     if (n32 > 0) {
       int64_t mv32 = 0, nl32 = 0;
-      const c32* A32 = w->A32;
+      const c32* H32 = A32;
+      const int64_t ld32 = lda32;
       void* tw = w->tail_ws;
       int* tc = w->tail_counters;
       auto launch = [&](const CGemmArgs& a) {
         CGemmArgs b = a;
-        b.A = A32;
-        b.lda = N;
+        b.A = H32;
+        b.lda = ld32;
         return cfilter_big_launch(b, s, tw, tc);
       };
       if ((st = run_filter_lowp(N, V + (int64_t)(locked + n16) * ldv, ldv, w->X32a, w->X32b, n32,
@@ -1119,7 +1160,7 @@ struct ProblemState {
       if (!std::isfinite(th_h[j]) || !std::isfinite(rs_h[j])) breakdown = true;
     }
     if (breakdown) return kOk;
-    if (mixed)  // a column moves down a rung at the rung's floor or once it stops improving
+    if (mixed && !w->c64)  // a column moves down a rung at the rung's floor or once it stops improving
       for (int j = locked; j < ne; ++j) {
         const bool stalled = resd[j] > 0.5 * prev_resd[j];
         if (low[j] == 2 && (resd[j] <= sw16_abs || stalled)) low[j] = 1;
@@ -1204,6 +1245,7 @@ struct chase_handle_s {
   Workspace w;
   chase_params_t p;
   bool real = false;  // created by chase_create_real
+  bool c64 = false;   // created by chase_create_c64
   int trace_level = 0;
   std::vector<chase_trace_t> trace;  // of the last solve
 };
@@ -1258,7 +1300,7 @@ int chase_destroy(chase_handle_t h) {
 int chase_solve(chase_handle_t h, const void* A_, int64_t lda, void* V_, int64_t ldv, int32_t use_v0,
                 const void* starts_, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
                 chase_stats_t* stats, chase_stream_t stream_) {
-  if (!h || h->real) return -1;
+  if (!h || h->real || h->c64) return -1;
   int st = check_solve_args(h->w.N, A_, lda, V_, ldv, starts_, ld_starts, nstarts, ritzv, resid);
   if (st) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
@@ -1390,6 +1432,83 @@ int chase_solve_real(chase_handle_t h, const double* A, int64_t lda, double* V, 
   t_all.destroy();
   ps.destroy_timers();
   w.Hr = nullptr;
+  if (st) return st;
+  if (stats) *stats = ps.S;
+  return ps.S.status;
+}
+
+int chase_create_c64(int64_t N, const chase_params_t* p, chase_handle_t* h) {
+  if (N < 2) return -1;
+  if (!valid_params(p) || (int64_t)p->nev + p->nex >= N || p->precision == CHASE_BF16X3_MIXED) return -2;
+  if (!h) return -3;
+  auto* hh = new chase_handle_s();
+  hh->p = *p;
+  hh->c64 = true;
+  int st = hh->w.create_c64(N, p->nev + p->nex);
+  if (st) {
+    delete hh;
+    *h = nullptr;
+    return st;
+  }
+  *h = hh;
+  return kOk;
+}
+
+int chase_solve_c64(chase_handle_t h, const void* A, int64_t lda, void* V, int64_t ldv, int32_t use_v0,
+                    const void* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
+                    chase_stats_t* stats, chase_stream_t stream_) {
+  if (!h || !h->c64) return -1;
+  Workspace& w = h->w;
+  const int64_t N = w.N;
+  int st = check_solve_args(N, A, lda, V, ldv, starts, ld_starts, nstarts, ritzv, resid);
+  if (st) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+  const int ne = h->p.nev + h->p.nex;
+  w.H32 = reinterpret_cast<const c32*>(A);
+  w.ldh32 = lda;
+  if (use_v0 && (st = convert_c_to_z(reinterpret_cast<const c32*>(V), ldv, w.Cint, N, N, ne, s))) return st;
+  const z64* starts64 = nullptr;
+  if (starts) {
+    if ((st = convert_c_to_z(reinterpret_cast<const c32*>(starts), ld_starts, w.lzW, N, N, nstarts, s))) return st;
+    starts64 = w.lzW;
+  }
+  ProblemState ps;
+  ps.w = &w;
+  ps.P = h->p;
+  ps.trace_level = h->trace_level;
+  ps.trace = &h->trace;
+  h->trace.clear();
+  ps.A = nullptr;  // every product with H goes through the FP32 kernels
+  ps.lda = 0;
+  ps.V = w.Cint;
+  ps.ldv = N;
+  PhaseTimer t_all;
+  if ((st = t_all.init()) || (st = ps.init_timers())) {
+    t_all.destroy();
+    ps.destroy_timers();
+    return st;
+  }
+  auto run = [&]() -> int {
+    int r;
+    t_all.start(s);
+    if ((r = ps.setup(use_v0, starts64, N, nstarts, s))) return r;
+    while (ps.active()) {
+      if ((r = ps.prepare(s))) return r;
+      if ((r = ps.filter_eager(s))) return r;
+      if ((r = ps.post_filter(s))) return r;
+    }
+    if ((r = ps.finish(ritzv, resid, s))) return r;
+    if ((r = convert_z_to_c(w.Cint, N, reinterpret_cast<c32*>(V), ldv, N, ne, s))) return r;
+    t_all.stop(s);
+    CHASE_CHK(hipStreamSynchronize(s));
+    t_all.collect();
+    return kOk;
+  };
+  st = run();
+  ps.S.t_total = t_all.acc;
+  t_all.destroy();
+  ps.destroy_timers();
+  w.H32 = nullptr;
   if (st) return st;
   if (stats) *stats = ps.S;
   return ps.S.status;

@@ -167,6 +167,9 @@ int copy_columns(const z64* src, int64_t lds, z64* dst, int64_t ldd, int64_t N, 
 // W = A V for Hermitian A (reads A's columns), V: N x nv (nv <= 8).
 int hemv_block(const z64* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int64_t ldw,
                int64_t N, int nv, hipStream_t s);
+// The same for complex64 H (products accumulated in FP64).
+int hemv_block_c64(const c32* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int64_t ldw,
+                   int64_t N, int nv, hipStream_t s);
 // One Lanczos step for nv independent vectors (see small.hip).
 int lanczos_step(z64* V, z64* Vold, z64* W, int64_t N, int nv, int step, int ksteps,
                  double* alpha, double* beta, hipStream_t s);

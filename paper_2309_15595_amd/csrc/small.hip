@@ -256,15 +256,18 @@ __global__ void c2z_kernel(const c32* src, int64_t lds, zv* dst, int64_t ldd, in
 
 // W[m, c] = sum_k A[m, k] V[k, c] = sum_k conj(A[k, m]) V[k, c]  (A Hermitian):
 // one wave per output row reads column m of A contiguously.
-__global__ __launch_bounds__(256) void hemv_kernel(const zv* A, int64_t lda, const zv* V, int64_t ldv, zv* W,
+// H's element type HT is complex128 (zv) or complex64 (c32, the complex64
+// variant); products accumulate in FP64 either way.
+template <class HT>
+__global__ __launch_bounds__(256) void hemv_kernel(const HT* A, int64_t lda, const zv* V, int64_t ldv, zv* W,
                                                    int64_t ldw, int64_t N, int nv) {
   const int lane = threadIdx.x & 63;
   const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (m >= N) return;
   double ar[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ai[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const zv* col = A + m * lda;
+  const HT* col = A + m * lda;
   for (int64_t k = lane; k < N; k += 64) {
-    zv a = col[k];
+    const zv a{(double)col[k].re, (double)col[k].im};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       if (c < nv) {
@@ -294,8 +297,8 @@ __global__ __launch_bounds__(256) void hemv_kernel(const zv* A, int64_t lda, con
 // read from L2 once per workgroup instead of once per column (at one column
 // per wave the re-reads of V outweighed the stream of H five to one).  H is
 // read once from HBM.
-template <int NV, int RPW>
-__global__ __launch_bounds__(256) void hemv_panel_kernel(const zv* __restrict__ A, int64_t lda,
+template <class HT, int NV, int RPW>
+__global__ __launch_bounds__(256) void hemv_panel_kernel(const HT* __restrict__ A, int64_t lda,
                                                          const zv* __restrict__ V, int64_t ldv, zv* W,
                                                          int64_t ldw, int64_t N) {
   constexpr int KC = 256;  // k per chunk
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(256) void hemv_panel_kernel(const zv* __restrict__ 
       for (int r = 0; r < RPW; ++r) {
         const int64_t m = m0 + r;
         if (m < N && k < N) {
-          const zv a = A[k + m * lda];  // conj(a) v
+          const zv a{(double)A[k + m * lda].re, (double)A[k + m * lda].im};  // conj(a) v
 #pragma unroll
           for (int c = 0; c < NV; ++c) {
             ar[r][c] += a.re * v[c].re + a.im * v[c].im;
@@ -629,21 +632,31 @@ int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N
   return kOk;
 }
 
-int hemv_block(const z64* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N, int nv,
-               hipStream_t s) {
+template <class HT>
+static int hemv_any(const HT* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N, int nv,
+                    hipStream_t s) {
   if (nv < 1 || nv > 8) return -1;
   if (nv == 4) {
     constexpr int RPW = 4;
-    hipLaunchKernelGGL((hemv_panel_kernel<4, RPW>), dim3((unsigned)cdiv(N, 4 * RPW)), dim3(256), 0, s,
-                       reinterpret_cast<const zv*>(A), lda, reinterpret_cast<const zv*>(V), ldv,
-                       reinterpret_cast<zv*>(W), ldw, N);
+    hipLaunchKernelGGL((hemv_panel_kernel<HT, 4, RPW>), dim3((unsigned)cdiv(N, 4 * RPW)), dim3(256), 0, s, A, lda,
+                       reinterpret_cast<const zv*>(V), ldv, reinterpret_cast<zv*>(W), ldw, N);
     CHASE_CHK_LAUNCH();
     return kOk;
   }
-  hipLaunchKernelGGL(hemv_kernel, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, reinterpret_cast<const zv*>(A), lda,
+  hipLaunchKernelGGL(hemv_kernel<HT>, dim3((unsigned)cdiv(N, 4)), dim3(256), 0, s, A, lda,
                      reinterpret_cast<const zv*>(V), ldv, reinterpret_cast<zv*>(W), ldw, N, nv);
   CHASE_CHK_LAUNCH();
   return kOk;
+}
+
+int hemv_block(const z64* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N, int nv,
+               hipStream_t s) {
+  return hemv_any(reinterpret_cast<const zv*>(A), lda, V, ldv, W, ldw, N, nv, s);
+}
+
+int hemv_block_c64(const c32* A, int64_t lda, const z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N, int nv,
+                   hipStream_t s) {
+  return hemv_any(A, lda, V, ldv, W, ldw, N, nv, s);
 }
 
 int symv_block(const double* H, int64_t ldh, const double* V, int64_t ldv, double* W, int64_t ldw, int64_t N,

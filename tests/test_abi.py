@@ -90,6 +90,8 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.chase_solve_real(None, None, 0, None, 0, 1, None, 0, 0, None, None, None, None) == -1
     assert lib.chase_filter_real(None, 2, None, 2, None, 2, 2, 1, None, 0.0, 1.0, -1.5, None, None) == -1
     assert lib.chase_create_real(1, None, None) == -1
+    assert lib.chase_create_c64(1, None, None) == -1
+    assert lib.chase_solve_c64(None, None, 0, None, 0, 1, None, 0, 0, None, None, None, None) == -1
     assert lib.chase_set_trace(None, 1) == -1
     assert lib.chase_get_trace(None, None, 0, None) == -1
     assert lib.chase_filter(None, 10, None, 10, None, 10, 10, 1, None, 0.0, 1.0, -1.0, None, None) == -1

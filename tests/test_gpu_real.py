@@ -103,7 +103,7 @@ def test_real_filter_rejects_odd_layout(L):
 
 def solve_real(p, **kw):
     from paper_2309_15595_amd.api import Solver
-    with Solver(p.N, p.nev, p.nex, real=True, **kw) as s:
+    with Solver(p.N, p.nev, p.nex, dtype=torch.float64, **kw) as s:
         Vd = cm(p.V0)
         ritz, resid, info = s.solve_colmajor(cm(p.A), Vd, True, cm(p.starts))
         X = un(Vd)[:, : p.nev]
@@ -154,7 +154,7 @@ def test_real_solve_random_start_and_trace(L):
     row must stay zero), and the trace's SVD on the real block."""
     from paper_2309_15595_amd.api import Solver
     p = synth.make_problem(301, 12, 6, spectrum="uniform", seed=9, real=True)
-    with Solver(p.N, p.nev, p.nex, real=True) as s:
+    with Solver(p.N, p.nev, p.nex, dtype=torch.float64) as s:
         s.set_trace(2)
         Vd = torch.empty((p.ne, p.N), dtype=torch.float64, device="cuda")
         ritz, resid, info = s.solve_colmajor(cm(p.A), Vd, False, None)
@@ -171,7 +171,7 @@ def test_real_solve_random_start_and_trace(L):
 def test_real_handle_guards(L):
     from paper_2309_15595_amd.api import Solver
     p = synth.make_problem(64, 4, 4, seed=1, real=True)
-    with Solver(p.N, p.nev, p.nex, real=True) as s:
+    with Solver(p.N, p.nev, p.nex, dtype=torch.float64) as s:
         with pytest.raises(TypeError):   # complex data for a real handle
             s.solve_colmajor(torch.zeros((64, 64), dtype=torch.complex128, device="cuda"),
                              torch.zeros((8, 64), dtype=torch.complex128, device="cuda"))
@@ -179,7 +179,7 @@ def test_real_handle_guards(L):
         assert L.load().chase_solve(s.h, L.dptr(cm(p.A)), 64, L.dptr(cm(p.V0)), 64, 1, None, 0, 0,
                                     rz, rz, None, None) == -1
     with pytest.raises(ValueError):      # mixed precision is FP64-only on the real path
-        Solver(p.N, p.nev, p.nex, real=True, precision=L.CHASE_FP32_MIXED)
+        Solver(p.N, p.nev, p.nex, dtype=torch.float64, precision=L.CHASE_FP32_MIXED)
 
 
 def test_eigsh_real(L):
