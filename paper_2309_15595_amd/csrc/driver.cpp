@@ -199,6 +199,11 @@ struct Workspace {
   z64* T = nullptr;      // ne x ne scratch
   z64* ws = nullptr;     // split-K partials
   z64* tau = nullptr;    // Householder scalars (ne)
+  z64* hhV = nullptr;    // Householder QR scratch (hhqr.hip): N x panel
+  z64* hhT = nullptr;    // panels x panel x panel
+  z64* hhW = nullptr;    // 2 x panel x ne
+  double* hhpart = nullptr;
+  z64* hhrow = nullptr;
   double* theta = nullptr;
   double* resd = nullptr;
   double* E = nullptr;   // heevd off-diagonal workspace
@@ -268,6 +273,14 @@ struct Workspace {
     st = st ? st : alloc(&T, sq);
     st = st ? st : alloc(&ws, (size_t)zgemm_splitk_workspace(ne, ne, max_splits));
     st = st ? st : alloc(&tau, (size_t)ne);
+    {
+      const size_t hp = kHouseholderPanel, npan = (size_t)cdiv(ne, kHouseholderPanel);
+      st = st ? st : alloc(&hhV, (size_t)N * hp);
+      st = st ? st : alloc(&hhT, npan * hp * hp);
+      st = st ? st : alloc(&hhW, 2 * hp * (size_t)ne);
+      st = st ? st : alloc(&hhpart, (size_t)kHouseholderMaxWg * 2 * hp);
+      st = st ? st : alloc(&hhrow, hp);
+    }
     st = st ? st : alloc(&theta, (size_t)ne);
     st = st ? st : alloc(&resd, (size_t)ne);
     st = st ? st : alloc(&E, (size_t)ne);
@@ -591,32 +604,28 @@ static int cholqr_pass(Workspace& w, z64* X, int64_t ldx, int64_t n, bool shifte
 }
 
 static int householder(Workspace& w, z64* X, int64_t ldx, int64_t n, hipStream_t s) {
+  if (!w.real) {
+    HouseholderWs h;
+    h.V = w.hhV;
+    h.T = w.hhT;
+    h.W1 = w.hhW;
+    h.W2 = w.hhW + (int64_t)kHouseholderPanel * w.ne;
+    h.part = w.hhpart;
+    h.rowj = w.hhrow;
+    h.tau = w.tau;
+    h.Q = w.B;
+    h.splitk = w.ws;
+    return householder_qr(X, ldx, w.N, n, h, s);
+  }
+  // the real block (a zero padding row stays zero): LAPACK's real routines
   rocblas_set_stream(w.rb, s);
-  if (w.real) {  // the real block (a zero padding row stays zero)
-    double* Xr = reinterpret_cast<double*>(X);
-    double* tau = reinterpret_cast<double*>(w.tau);
-    rocblas_status r = rocsolver_dgeqrf(w.rb, (rocblas_int)(2 * w.N), (rocblas_int)n, Xr, (rocblas_int)(2 * ldx), tau);
-    if (r == rocblas_status_success)
-      r = rocsolver_dorgqr(w.rb, (rocblas_int)(2 * w.N), (rocblas_int)n, (rocblas_int)n, Xr, (rocblas_int)(2 * ldx),
-                           tau);
-    if (r != rocblas_status_success) {
-      set_msg("rocsolver_dgeqrf/dorgqr failed");
-      return kHipError;
-    }
-    return kOk;
-  }
-  rocblas_status r = rocsolver_zgeqrf(w.rb, (rocblas_int)w.N, (rocblas_int)n,
-                                      reinterpret_cast<rocblas_double_complex*>(X), (rocblas_int)ldx,
-                                      reinterpret_cast<rocblas_double_complex*>(w.tau));
+  double* Xr = reinterpret_cast<double*>(X);
+  double* tau = reinterpret_cast<double*>(w.tau);
+  rocblas_status r = rocsolver_dgeqrf(w.rb, (rocblas_int)(2 * w.N), (rocblas_int)n, Xr, (rocblas_int)(2 * ldx), tau);
+  if (r == rocblas_status_success)
+    r = rocsolver_dorgqr(w.rb, (rocblas_int)(2 * w.N), (rocblas_int)n, (rocblas_int)n, Xr, (rocblas_int)(2 * ldx), tau);
   if (r != rocblas_status_success) {
-    set_msg("rocsolver_zgeqrf failed");
-    return kHipError;
-  }
-  r = rocsolver_zungqr(w.rb, (rocblas_int)w.N, (rocblas_int)n, (rocblas_int)n,
-                       reinterpret_cast<rocblas_double_complex*>(X), (rocblas_int)ldx,
-                       reinterpret_cast<rocblas_double_complex*>(w.tau));
-  if (r != rocblas_status_success) {
-    set_msg("rocsolver_zungqr failed");
+    set_msg("rocsolver_dgeqrf/dorgqr failed");
     return kHipError;
   }
   return kOk;

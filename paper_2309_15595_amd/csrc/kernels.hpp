@@ -143,6 +143,24 @@ int64_t bsplit_ld(int64_t N);
 int bsplit_planes(const z64* H, int64_t lda, int64_t N, uint16_t* P, hipStream_t s);
 int bfilter_launch(const BGemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters);
 
+// ---- Householder QR (hhqr.hip) ---------------------------------------------
+// Blocked Householder QR of the M x n block X (n <= M) in LAPACK's
+// conventions, then X <- the explicit M x n factor Q.  Device scratch:
+constexpr int kHouseholderPanel = 32;
+constexpr int kHouseholderMaxWg = 128;  // workgroups per reflector launch
+struct HouseholderWs {
+  z64* V = nullptr;       // M x panel (explicit reflectors of one panel)
+  z64* T = nullptr;       // cdiv(n, panel) x panel x panel (block reflector factors)
+  z64* W1 = nullptr;      // panel x n
+  z64* W2 = nullptr;      // panel x n
+  double* part = nullptr; // kHouseholderMaxWg x 2 panel partial sums
+  z64* rowj = nullptr;    // panel
+  z64* tau = nullptr;     // n
+  z64* Q = nullptr;       // M x n (leading dimension M)
+  z64* splitk = nullptr;  // split-K partials: 16 x panel x n
+};
+int householder_qr(z64* X, int64_t ldx, int64_t M, int64_t n, const HouseholderWs& ws, hipStream_t s);
+
 // ---- small dense kernels (small.hip) --------------------------------------
 // Blocked lower Cholesky G = L L^H in place (lower part), n x n, ld.
 // *info (device) receives 0, or j+1 for the first non-positive pivot j.

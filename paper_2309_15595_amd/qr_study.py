@@ -6,7 +6,7 @@
     columns, with and without degree optimisation.
   * QR variants (the comparison of Table 2): time to solution, QR time,
     iterations and MatVecs with the CondEst-driven choice of Alg. 4 and with
-    each variant forced, Householder QR included.
+    each variant forced, the blocked Householder QR included.
 
 The workload is the synthetic Hermitian problem of the filter benchmark
 (complex128, a spectrum shaped like a DFT Hamiltonian's, Gaussian random

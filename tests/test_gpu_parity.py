@@ -128,9 +128,23 @@ def test_caqr_matches_oracle(L, kappa, force):
     assert np.linalg.norm(Q @ R - X) <= 1e-12 * np.linalg.norm(X)
     ref, vref = oc.caqr(X, kappa, None if force < 0 else force)
     assert v == vref
-    if v != oc.QR_HOUSEHOLDER:
-        # CholeskyQR's Q is unique: compare element by element
-        assert np.max(np.abs(Q - ref)) <= max(1e-12, 1e-14 * kappa * n) , np.max(np.abs(Q - ref))
+    # CholeskyQR's Q is unique; the Householder branch follows LAPACK's
+    # reflector conventions, so its Q is the oracle's (LAPACK's) one
+    assert np.max(np.abs(Q - ref)) <= max(1e-12, 1e-14 * kappa * n), np.max(np.abs(Q - ref))
+
+
+@pytest.mark.parametrize("m,n", [(1000, 300), (333, 37), (96, 96), (517, 1), (2000, 64)])
+def test_householder_qr_matches_lapack(L, m, n):
+    """Blocked Householder QR (panels of 32, ragged last panel, one reflector
+    per column) against LAPACK's Q element by element."""
+    X = pins.matrix_with_cond(m, n, 1e4, seed=m + n)
+    Xd = cm(X)
+    v = L.chase_caqr(L.dptr(Xd), m, m, n, 1.0, oc.QR_HOUSEHOLDER, sp())
+    assert v == oc.QR_HOUSEHOLDER
+    Q = un(Xd)
+    ref = oc.householder_qr(X)
+    assert np.max(np.abs(Q - ref)) <= 1e-14 * 1e4 * max(n, 10), np.max(np.abs(Q - ref))
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(n), 2) <= 1e-13
 
 
 def test_caqr_fallback_rank_deficient(L):
