@@ -71,6 +71,62 @@ def test_dft_20000_fp64_and_mixed(L):
     assert _ortho(V32, nev) <= 1e-12
 
 
+def test_real_20000(L):
+    """The real symmetric variant at N = 20000 on the same spectrum (the
+    matrix built with the DCT-sign rotation): prescribed spectrum, reported
+    residuals, orthogonality, and sampled residuals recomputed one by one."""
+    from paper_2309_15595_amd.api import Solver
+    N, nev, nex = 20000, 1000, 300
+    lam = synth.dft_like_spectrum(N)
+    A = sp.symmetric_from_spectrum_torch(lam, seed=sp.SEED_Q, device="cuda")
+    V = torch.from_numpy(np.ascontiguousarray(
+        synth.real_gaussian(np.random.default_rng(sp.SEED_V0), (N, nev + nex)).T)).cuda()
+    S = torch.from_numpy(np.ascontiguousarray(
+        synth.real_gaussian(np.random.default_rng(sp.SEED_LANCZOS), (N, 4)).T)).cuda()
+    normA = float(np.max(np.abs(lam)))
+    with Solver(N, nev, nex, dtype=torch.float64) as s:
+        ritz, resid, info = s.solve_colmajor(A, V, True, S)
+    assert info.converged
+    assert np.max(np.abs(ritz - lam[:nev])) <= 1e-10 * normA
+    assert np.max(resid) <= 1e-10 * normA
+    assert _ortho(V, nev) <= 1e-12
+    for j in (0, nev // 2, nev - 1):
+        r = A @ V[j] - ritz[j] * V[j]
+        assert abs(float(torch.linalg.vector_norm(r)) - resid[j]) <= 1e-12 * normA
+    st = info.stats
+    print(f"\nreal N=20000: {st['t_total']:.2f} s, filter {st['filter_flops'] / st['t_filter'] / 1e12:.1f} "
+          f"TFLOP/s, {st['iterations']} iterations")
+
+
+def test_c64_20000(L):
+    """The complex64 variant at N = 20000 (the matrix rounded to complex64,
+    tol 2e-5): spectrum within 1e-6 ||H||, sampled residuals of the returned
+    complex64 vectors recomputed in FP64 against the complex64 matrix."""
+    from paper_2309_15595_amd.api import Solver
+    N, nev, nex, tol = 20000, 1000, 300, 2e-5
+    lam = synth.dft_like_spectrum(N)
+    A = sp.hermitian_from_spectrum_torch(lam, seed=sp.SEED_Q, device="cuda").to(torch.complex64)
+    V = torch.from_numpy(np.ascontiguousarray(
+        synth.complex_gaussian(np.random.default_rng(sp.SEED_V0), (N, nev + nex)).T)).to(torch.complex64).cuda()
+    S = torch.from_numpy(np.ascontiguousarray(
+        synth.complex_gaussian(np.random.default_rng(sp.SEED_LANCZOS), (N, 4)).T)).to(torch.complex64).cuda()
+    normA = float(np.max(np.abs(lam)))
+    with Solver(N, nev, nex, dtype=torch.complex64, tol=tol) as s:
+        ritz, resid, info = s.solve_colmajor(A, V, True, S)
+    assert info.converged
+    assert np.max(np.abs(ritz - lam[:nev])) <= 1e-6 * normA
+    assert np.max(resid) <= tol * normA
+    A64 = A.to(torch.complex128)
+    for j in (0, nev // 2, nev - 1):
+        x = V[j].to(torch.complex128)   # the solved matrix is conj(A) (row-major memory read column-major)
+        r = torch.conj(A64 @ torch.conj(x)) - ritz[j] * x
+        assert float(torch.linalg.vector_norm(r)) <= 2 * tol * normA
+    del A64
+    st = info.stats
+    print(f"\ncomplex64 N=20000: {st['t_total']:.2f} s, FP32 filter "
+          f"{st['filter_flops'] / st['t_filter'] / 1e12:.1f} TFLOP/s, {st['iterations']} iterations")
+
+
 def test_batched_64_problems(L):
     """64 problems, N ~ U[2000, 12000], nev = N/20, nex = N/80, DFT-like
     spectra with per-problem seeds, one grouped solve."""
