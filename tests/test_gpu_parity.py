@@ -364,6 +364,37 @@ def test_householder_same_path_as_cholesky(L, parity_problem, parity_oracle):
     assert info_h.stats["qr_count"][3] == info_h.stats["iterations"]
 
 
+def test_warm_start(L, parity_problem, parity_oracle):
+    """Approximate eigenvectors as the initial block (Sec. 1): the exact ones
+    converge in one iteration; the solution of the unperturbed problem
+    started on a perturbed one converges in fewer iterations than a random
+    block, to the oracle's eigenvalues of the perturbed matrix."""
+    p = parity_problem
+    w, Q = np.linalg.eigh(p.A)
+    from dataclasses import replace
+    exact = replace(p, V0=Q[:, : p.ne])
+    ritz, resid, X, info = solve_gpu(exact)
+    assert info.converged and info.stats["iterations"] == 1
+    assert np.max(np.abs(ritz - w[: p.nev])) <= 1e-13
+    # a nearby Hermitian matrix, warm-started from p's converged block
+    E = synth.complex_gaussian(np.random.default_rng(77), (p.N, p.N))
+    A2 = p.A + 1e-4 * (E + E.conj().T) / np.sqrt(p.N)
+    from paper_2309_15595_amd.api import Solver
+    with Solver(p.N, p.nev, p.nex) as s:
+        Vd = cm(p.V0)
+        s.solve_colmajor(cm(p.A), Vd, True, cm(p.starts))          # p's solution in Vd
+        r_warm, _, i_warm = s.solve_colmajor(cm(A2), Vd, True, cm(p.starts))
+        r_cold, _, i_cold = s.solve_colmajor(cm(A2), cm(p.V0), True, cm(p.starts))
+    assert i_warm.converged and i_cold.converged
+    ref = oc.chase(A2, oc.Params(nev=p.nev, nex=p.nex), V0=p.V0, starts=p.starts)
+    assert np.max(np.abs(r_warm - ref.evals)) <= 1e-10 * p.norm2
+    assert np.max(np.abs(r_cold - ref.evals)) <= 1e-10 * p.norm2
+    print(f"\nwarm start: {i_warm.stats['iterations']} iterations, "
+          f"{i_warm.stats['filter_matvecs']} MatVecs; cold: {i_cold.stats['iterations']}, "
+          f"{i_cold.stats['filter_matvecs']}")
+    assert i_warm.stats["filter_matvecs"] < i_cold.stats["filter_matvecs"]
+
+
 def test_solve_not_converged_status(L, parity_problem):
     ritz, resid, X, info = solve_gpu(parity_problem, max_iter=1)
     assert info.status == 1 and not info.converged

@@ -144,6 +144,18 @@ def test_condest_bounds_computed_condition(parity_problem, opt):
             assert est >= kappa(X), (h["iteration"], est)
 
 
+def test_warm_start_from_exact_eigenvectors(parity_problem):
+    """Approximate eigenvectors may be passed in (Sec. 1, Alg. 1's initial
+    block): started from the exact lowest n_e eigenvectors, the filter and
+    the QR keep their span, Rayleigh-Ritz returns the exact pairs and every
+    wanted pair locks in the first iteration."""
+    p = parity_problem
+    w, Q = np.linalg.eigh(p.A)
+    r = oc.chase(p.A, oc.Params(nev=p.nev, nex=p.nex), V0=Q[:, : p.ne], starts=p.starts)
+    assert r.converged and r.iterations == 1
+    assert np.max(np.abs(r.evals - w[: p.nev])) <= 1e-13
+
+
 def test_householder_same_matvecs(parity_problem, parity_oracle):
     """CholeskyQR and Householder QR give the same MatVecs and iteration
     counts (Sec. 4.3, Table 2 discussion)."""
