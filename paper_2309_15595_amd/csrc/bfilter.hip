@@ -14,12 +14,19 @@
 // Im lo) of conj(H) in H's own memory order: H is Hermitian, so column m of
 // the stored matrix, conjugated, is row m of H, and each output row then
 // reads K-contiguous runs.  Rows are padded to a multiple of 32 with zeros.
+// The block X comes as the same four planes, column by column: each step's
+// epilogue writes the planes of its output beside the FP32 result, so the
+// split happens once per element and step.  (Splitting in the consumer
+// repeats it for every 128-row panel of H, and measured as the larger part
+// of the step's time.)
 //
 // Tiling: 128 (m) x 128 (n) complex tile, 8 waves of 64 x 32, K tile 32 (one
-// MFMA K step).  LDS holds two K tiles of the four H planes and the four X
-// planes (bf16, 64-byte rows, 16-byte chunks XOR-swizzled by row so that the
-// 16 lanes of a fragment read hit distinct banks): 128 KB.  The last partial
-// round of tiles is split along K as in the FP64 kernel.  The MFMA row index
+// MFMA K step).  Both operands go from memory straight to LDS
+// (global_load_lds_dwordx4, 16 bytes per lane: 8 k of one plane of one row),
+// two K tiles of the four H planes and the four X planes (bf16, 64-byte rows,
+// 16-byte chunks XOR-swizzled by row so that the 16 lanes of a fragment read
+// hit distinct banks): 128 KB.  The last partial round of tiles is split
+// along K as in the FP64 kernel.  The MFMA row index
 // is the output column n and the column index the output row m; the f32
 // accumulator layout (lane l, element r: row 4 (l/16) + r, column l % 16)
 // was measured on gfx950.
@@ -54,8 +61,18 @@ struct BSmem {
 __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
 
 
+// The four bfloat16 planes of an output value, for the next step's X.
+__device__ __forceinline__ void store_planes(const BGemmArgs& g, int64_t m, int64_t n, cv v) {
+  const uint32_t a = bf16_bits(v.re), b = bf16_bits(v.im);
+  uint16_t* q = g.Yp + n * g.ldyp + m;
+  q[0] = (uint16_t)a;
+  q[g.yps] = (uint16_t)bf16_bits(v.re - bf16_value(a));
+  q[2 * g.yps] = (uint16_t)b;
+  q[3 * g.yps] = (uint16_t)bf16_bits(v.im - bf16_value(b));
+}
+
 // One 128 x 128 output tile over K range [kbeg, kend) (multiples of BK, kend
-// may exceed K: the planes are zero-padded and X loads are guarded).
+// may exceed K: both operands' planes are zero-padded in k).
 template <bool EDGE>
 __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn, int64_t kbeg, int64_t kend,
                                       cv* part, BSmem& s) {
@@ -78,60 +95,42 @@ __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn
       im[a][b] = f32x4{0, 0, 0, 0};
     }
 
-  // staging registers: one 8-k chunk of each H plane for row hx_m, and 8
-  // complex of X (column xn, chunk xkc); 4 consecutive threads cover a row
-  uint4 rh[4];
-  cv rx[8];
-  const int hx_m = t / 4, hx_c = t % 4;
-  const int xn = t / 4, xkc = t % 4;
-  auto gload = [&](int64_t k0) {
-    const int64_t m = m0 + hx_m;
+  // Loads of K tile [k0, k0 + 32) into buffer `buf`: 64 instructions, 8 per
+  // wave.  Instruction i moves 16 rows (H, i < 32) or 16 columns (X) of plane
+  // (i / 8) % 4; lane l takes row (column) 16 (i mod 8) + l / 4 and stores the
+  // chunk that belongs at position l % 4 of its swizzled row.  Rows past M and
+  // columns past N are not loaded (they only reach discarded outputs); k past
+  // K reads the planes' zero padding.
+  auto issue = [&](int64_t k0, int buf) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const uint4* row = reinterpret_cast<const uint4*>(g.P + (int64_t)p * g.plane_stride + m * g.ldp + k0);
-      rh[p] = (m < g.M) ? row[hx_c] : uint4{0, 0, 0, 0};
+    for (int r = 0; r < 8; ++r) {
+      const int i = wave * 8 + r;
+      const bool is_h = i < 32;
+      const int p = (i >> 3) & 3, r0 = (i & 7) << 4;
+      const int row = r0 + (lane >> 2);
+      const int c = (lane & 3) ^ ((row >> 2) & 3);  // chunk stored at position lane & 3
+      if (is_h) {
+        const int64_t m = m0 + row;
+        if (!EDGE || m < g.M)
+          __builtin_amdgcn_global_load_lds(g.P + p * g.plane_stride + m * g.ldp + k0 + 8 * c, &s.h[buf][p][r0][0],
+                                           16, 0, 0);
+      } else {
+        const int64_t n = n0 + row;
+        if (!EDGE || n < g.N)
+          __builtin_amdgcn_global_load_lds(g.Xp + p * g.xps + n * g.ldxp + k0 + 8 * c, &s.x[buf][p][r0][0], 16, 0,
+                                           0);
+      }
     }
-    const int64_t n = n0 + xn;
-    const cv* col = reinterpret_cast<const cv*>(g.X) + n * g.ldx + k0 + 8 * xkc;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const int64_t k = k0 + 8 * xkc + v;
-      rx[v] = (n < g.N && k < g.K) ? col[v] : cv{0.f, 0.f};
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p) s.h[buf][p][hx_m][swz(hx_m, hx_c)] = rh[p];
-    uint32_t rh_[8], rl_[8], ih_[8], il_[8];
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const uint32_t a = bf16_bits(rx[v].re), b = bf16_bits(rx[v].im);
-      rh_[v] = a;
-      rl_[v] = bf16_bits(rx[v].re - bf16_value(a));
-      ih_[v] = b;
-      il_[v] = bf16_bits(rx[v].im - bf16_value(b));
-    }
-    auto pack = [](const uint32_t* w) {
-      return uint4{w[0] | (w[1] << 16), w[2] | (w[3] << 16), w[4] | (w[5] << 16), w[6] | (w[7] << 16)};
-    };
-    const int c = swz(xn, xkc);
-    s.x[buf][0][xn][c] = pack(rh_);
-    s.x[buf][1][xn][c] = pack(rl_);
-    s.x[buf][2][xn][c] = pack(ih_);
-    s.x[buf][3][xn][c] = pack(il_);
   };
 
   const int64_t nkt = (kend - kbeg) / BK;
-  if (nkt > 0) {
-    gload(kbeg);
-    sstore(0);
-    if (nkt > 1) gload(kbeg + BK);
-  }
+  if (nkt > 0) issue(kbeg, 0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  // Row block at which the wave stores the next K-tile and loads the one
-  // after: waves w and w + 4 share a SIMD; staggering them keeps one wave's
-  // store / load issue under the other's MFMAs.
-  const int stage_at = wave >= 4 ? TM / 2 : 0;
+  // Row block at which the wave issues the next K tile: waves w and w + 4
+  // share a SIMD; staggering them keeps one wave's load issue under the
+  // other's MFMAs.
+  const int issue_at = wave >= 4 ? TM / 2 : 0;
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int buf = (int)(kt & 1);
     {
@@ -150,10 +149,7 @@ __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn
 #pragma unroll
       for (int mb = 0; mb < TM; ++mb) {
         // buffer buf ^ 1 was last read before the previous barrier
-        if (mb == stage_at && kt + 1 < nkt) {
-          sstore(buf ^ 1);
-          if (kt + 2 < nkt) gload(kbeg + (kt + 2) * BK);
-        }
+        if (mb == issue_at && kt + 1 < nkt) issue(kbeg + (kt + 1) * BK, buf ^ 1);
         if (!active) continue;
         const int m = wm * 64 + mb * 16 + l16;
         bf16x8 hf[4];
@@ -169,6 +165,7 @@ __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn
 #undef BMMA
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next K tile have landed
     __syncthreads();
   }
 
@@ -208,6 +205,7 @@ __device__ __forceinline__ void btile(const BGemmArgs& g, int64_t tm, int64_t tn
           out.im += g.gamma * z.im;
         }
         Y[m + n * g.ldy] = out;
+        store_planes(g, m, n, out);
       }
 }
 
@@ -252,6 +250,7 @@ __device__ __forceinline__ void barrive(const BGemmArgs& g, const TailSplit& tai
       out.im += g.gamma * z.im;
     }
     Y[m + n * g.ldy] = out;
+    store_planes(g, m, n, out);
   }
   if (threadIdx.x == 0) tail.counters[tl] = 0;
 }
@@ -296,6 +295,20 @@ __global__ void bsplit_kernel(const double* H, int64_t lda, int64_t N, uint16_t*
   P[3 * plane_stride + o] = (uint16_t)il;
 }
 
+// The four planes of a complex64 block (rows padded with zeros to ldxp).
+__global__ void bsplit_x_kernel(const cv* X, int64_t ldx, int64_t rows, uint16_t* Xp, int64_t ldxp, int64_t xps) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = blockIdx.y;
+  if (k >= ldxp) return;
+  const cv v = k < rows ? X[k + n * ldx] : cv{0.f, 0.f};
+  const uint32_t a = bf16_bits(v.re), b = bf16_bits(v.im);
+  uint16_t* q = Xp + n * ldxp + k;
+  q[0] = (uint16_t)a;
+  q[xps] = (uint16_t)bf16_bits(v.re - bf16_value(a));
+  q[2 * xps] = (uint16_t)b;
+  q[3 * xps] = (uint16_t)bf16_bits(v.im - bf16_value(b));
+}
+
 static int cu_count_b() {
   static int cus = 0;
   if (cus == 0) {
@@ -319,9 +332,24 @@ int bsplit_planes(const z64* H, int64_t lda, int64_t N, uint16_t* P, hipStream_t
   return kOk;
 }
 
+int bsplit_block(const c32* X, int64_t ldx, int64_t rows, int64_t ncols, uint16_t* Xp, int64_t ldxp, int64_t xps,
+                 hipStream_t s) {
+  if (ncols <= 0) return kOk;
+  if (ldxp < rows || ldxp % BK) return -1;
+  hipLaunchKernelGGL(bsplit_x_kernel, dim3((unsigned)cdiv(ldxp, 256), (unsigned)ncols), dim3(256), 0, s,
+                     reinterpret_cast<const cv*>(X), ldx, rows, Xp, ldxp, xps);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
 int bfilter_launch(const BGemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters) {
   if (g.M <= 0 || g.N <= 0) return kOk;
   if (!tail_ws || !tail_counters) return -1;
+  // 16-byte DMA lanes: plane rows / columns padded to whole K tiles, aligned
+  if (!g.Xp || !g.Yp || g.ldp % BK || g.ldxp % BK || g.ldxp < g.K || g.ldp < g.K ||
+      reinterpret_cast<uintptr_t>(g.P) % 16 || reinterpret_cast<uintptr_t>(g.Xp) % 16 || g.plane_stride % 8 ||
+      g.xps % 8)
+    return -1;
   TileGeom geo;  // 8 waves of 64 x 32: wave w at (w & 1, w >> 1)
   geo.M = g.M; geo.N = g.N; geo.bm = BM; geo.bn = BN; geo.wgm = 2; geo.wgn = 4;
   TailSplit t;

@@ -223,6 +223,8 @@ struct Workspace {
   c32* X32b = nullptr;
   uint16_t* P16 = nullptr;     // BF16x3 planes of conj(H) (4 x ldp x N)
   int64_t ldp = 0;
+  uint16_t* XP16a = nullptr;   // BF16x3 planes of X32a / X32b (4 x ldp x ne each, k padding zero)
+  uint16_t* XP16b = nullptr;
   void* tail_ws = nullptr;     // split-K tail of the big GEMMs
   int* tail_counters = nullptr;
   z64* tune_scratch = nullptr; // autotuner output sink (N x ne), allocated on first use
@@ -308,6 +310,13 @@ struct Workspace {
     if (bf16) {
       ldp = bsplit_ld(N);
       st = st ? st : alloc(&P16, (size_t)4 * ldp * N);
+      st = st ? st : alloc(&XP16a, (size_t)4 * ldp * ne);
+      st = st ? st : alloc(&XP16b, (size_t)4 * ldp * ne);
+      if (!st && (hipMemset(XP16a, 0, sizeof(uint16_t) * 4 * ldp * ne) != hipSuccess ||
+                  hipMemset(XP16b, 0, sizeof(uint16_t) * 4 * ldp * ne) != hipSuccess)) {
+        set_msg("hipMemset failed");
+        st = kHipError;
+      }
     }
     if (!st && rocblas_create_handle(&rb) != rocblas_status_success) {
       set_msg("rocblas_create_handle failed");
@@ -496,10 +505,11 @@ static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, in
 // Low-precision filter for the columns still on an FP32 or BF16x3 rung: the
 // same recurrence and scalars as plan_filter, on complex64 copies of the
 // columns (X0/X1 ping-pong), converted back to complex128 as each column
-// reaches its degree.  `launch` runs one step's GEMM.
+// reaches its degree.  `launch` runs one step's GEMM; it is told which buffer
+// the step reads and the step's first column.
 static int run_filter_lowp(int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int64_t n, const int32_t* degs,
                            double c, double e, double mu1, int64_t* matvecs, int64_t* launches, hipStream_t s,
-                           const std::function<int(const CGemmArgs&)>& launch) {
+                           const std::function<int(const CGemmArgs&, bool, int64_t)>& launch) {
   if (n <= 0) return kOk;
   int st = convert_z_to_c(V, ldv, X0, N, N, n, s);
   if (st) return st;
@@ -538,7 +548,7 @@ static int run_filter_lowp(int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int
     g.Y = out + s0 * N; g.ldy = N;
     g.Z = cur + s0 * N; g.ldz = N;
     g.alpha = (float)alpha; g.beta = (float)beta; g.gamma = (float)(-alpha * c);
-    st = launch(g);
+    st = launch(g, cur0, s0);  // cur0: the step reads X0; s0: its first column
     if (st) return st;
     mv += cols;
     ++nl;
@@ -1058,7 +1068,16 @@ struct ProblemState {
       const int64_t ldp = w->ldp;
       void* tw = w->tail_ws;
       int* tc = w->tail_counters;
-      auto launch = [&](const CGemmArgs& a) {
+      // the bfloat16 planes of the two complex64 buffers, column for column
+      uint16_t* const XP[2] = {w->XP16a, w->XP16b};
+      const int64_t xps = ldp * ne;
+      bool first = true;
+      auto launch = [&](const CGemmArgs& a, bool cur0, int64_t s0) {
+        int r;
+        if (first) {  // planes of the starting block (step 0 reads X0 from column 0)
+          first = false;
+          if ((r = bsplit_block(a.B, a.ldb, a.K, a.N, XP[0], ldp, xps, s))) return r;
+        }
         BGemmArgs b;
         b.M = a.M; b.N = a.N; b.K = a.K;
         b.P = P16; b.ldp = ldp; b.plane_stride = ldp * N;
@@ -1066,6 +1085,8 @@ struct ProblemState {
         b.Y = a.Y; b.ldy = a.ldy;
         b.Z = a.Z; b.ldz = a.ldz;
         b.alpha = a.alpha; b.beta = a.beta; b.gamma = a.gamma;
+        b.Xp = XP[cur0 ? 0 : 1] + s0 * ldp; b.ldxp = ldp; b.xps = xps;
+        b.Yp = XP[cur0 ? 1 : 0] + s0 * ldp; b.ldyp = ldp; b.yps = xps;
         return bfilter_launch(b, s, tw, tc);
       };
       if ((st = run_filter_lowp(N, V + (int64_t)locked * ldv, ldv, w->X32a, w->X32b, n16, degs.data() + locked,
@@ -1081,7 +1102,7 @@ struct ProblemState {
       const int64_t ld32 = lda32;
       void* tw = w->tail_ws;
       int* tc = w->tail_counters;
-      auto launch = [&](const CGemmArgs& a) {
+      auto launch = [&](const CGemmArgs& a, bool, int64_t) {
         CGemmArgs b = a;
         b.A = H32;
         b.lda = ld32;

@@ -138,8 +138,16 @@ struct BGemmArgs {
   c32* Y = nullptr;       int64_t ldy = 0;
   const c32* Z = nullptr; int64_t ldz = 0;
   float alpha = 1.f, beta = 0.f, gamma = 0.f;
+  // bfloat16 planes (Re hi, Re lo, Im hi, Im lo) of X (read) and of Y
+  // (written with Y): column n of plane p at Xp + p xps + n ldxp, k padded
+  // with zeros to a multiple of 32 (ldxp)
+  const uint16_t* Xp = nullptr; int64_t ldxp = 0; int64_t xps = 0;
+  uint16_t* Yp = nullptr;       int64_t ldyp = 0; int64_t yps = 0;
 };
 int64_t bsplit_ld(int64_t N);
+// The planes of a complex64 block (rows x ncols, rows padded with zeros to ldxp).
+int bsplit_block(const c32* X, int64_t ldx, int64_t rows, int64_t ncols, uint16_t* Xp, int64_t ldxp, int64_t xps,
+                 hipStream_t s);
 int bsplit_planes(const z64* H, int64_t lda, int64_t N, uint16_t* P, hipStream_t s);
 int bfilter_launch(const BGemmArgs& g, hipStream_t s, void* tail_ws, int* tail_counters);
 
