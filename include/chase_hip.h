@@ -10,9 +10,10 @@
  * identity and B2 aliases C2).
  *
  * Conventions for every entry point:
- *   - matrices are column-major complex128 ((re, im) double pairs), with a
- *     leading dimension >= the row count, addressed by DEVICE pointers unless
- *     an argument says (host);
+ *   - matrices are column-major complex128 ((re, im) double pairs) unless the
+ *     entry point says float64 (the real symmetric variant) or complex64, with
+ *     a leading dimension >= the row count, addressed by DEVICE pointers
+ *     unless an argument says (host);
  *   - device pointers must be 16-byte aligned;
  *   - sizes are int64_t;
  *   - work is ordered on `stream` after the caller's earlier work on it; an

@@ -2,10 +2,16 @@
 // 1 x 1 grid (AllReduce = identity, B2 = C2), host scalar logic (bounds,
 // degree optimisation, CondEst, locking decisions) and the C ABI.
 //
-// Device work all runs in the hand-written kernels of zgemm.hip, zfilter.hip
-// and small.hip, except the n_e x n_e Hermitian eigensolve of Rayleigh-Ritz
-// (rocSOLVER zheevd) and the rarely taken Householder-QR fallback of Alg. 4
-// (rocSOLVER zgeqrf/zungqr).
+// Device work all runs in the hand-written kernels of zgemm.hip, zfilter.hip,
+// bfilter.hip, zgrad.hip, hhqr.hip and small.hip, except the n_e x n_e
+// eigensolve of Rayleigh-Ritz (rocSOLVER zheevd / dsyevd), the real type
+// variant's Householder QR (rocSOLVER dgeqrf / dorgqr) and the trace's
+// singular values (rocSOLVER zgesvd / dgesvd, studies only).
+//
+// Three element types share the loop: complex128 (chase_solve), real
+// symmetric float64 (chase_solve_real: real columns read as complex row
+// pairs, see Workspace) and complex64 (chase_solve_c64: every column on the
+// FP32 rung, H in the caller's complex64 storage).
 #include "../../include/chase_hip.h"
 #include "common.hpp"
 #include "kernels.hpp"
