@@ -95,3 +95,29 @@ def test_c64_guards(L):
         rz = L.f64_array(4)
         assert L.load().chase_solve(s.h, L.dptr(cm64(p.A)), 64, L.dptr(cm64(p.V0)), 64, 1, None, 0, 0,
                                     rz, rz, None, None) == -1
+
+
+def test_c64_leading_dimension(L):
+    """lda, ldv > N and odd: the FP32 steps take the staged kernel; padding
+    rows of the block are untouched; the same pairs as the packed layout."""
+    from paper_2309_15595_amd.api import from_colmajor
+    p = synth.make_problem(256, 10, 6, spectrum="uniform", seed=5)
+    ld = p.N + 5
+    Abig = np.zeros((ld, p.N), dtype=np.complex64)
+    Abig[: p.N] = p.A
+    Vbig = np.full((ld, p.ne), 3.0 + 3.0j, dtype=np.complex64)
+    Vbig[: p.N] = p.V0
+    prm = L.default_params(nev=p.nev, nex=p.nex, tol=TOL)
+    h = L.chase_create_c64(p.N, prm)
+    try:
+        Ad, Vd, Sd = cm64(Abig), cm64(Vbig), cm64(p.starts)
+        ritz, resid, st = L.chase_solve_c64(h, L.dptr(Ad), ld, L.dptr(Vd), ld, 1, L.dptr(Sd), p.N, 4, p.nev,
+                                            L.stream_ptr())
+    finally:
+        L.chase_destroy(h)
+    assert st.status == 0
+    got = from_colmajor(Vd)
+    assert np.all(got[p.N:] == np.complex64(3.0 + 3.0j))
+    ref_ritz, _, _, _ = solve_c64(p)
+    assert np.max(np.abs(np.array(ritz) - ref_ritz)) <= 1e-6 * p.norm2
+    assert np.max(np.abs(np.array(ritz) - p.lam[: p.nev])) <= 1e-6 * p.norm2

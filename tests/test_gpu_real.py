@@ -193,3 +193,29 @@ def test_eigsh_real(L):
     lam = evals.cpu().numpy()
     assert np.max(np.abs(lam - p.lam[: p.nev])) <= 1e-10 * p.norm2
     assert np.max(np.linalg.norm(p.A @ X - X * lam, axis=0)) <= 1e-10 * p.norm2 * (1 + 1e-6)
+
+
+def test_real_solve_odd_leading_dimension(L):
+    """Even order with an odd leading dimension (the padded copy of H) and a
+    block with its own padding rows, through the C ABI: the same pairs as the
+    in-place layout."""
+    p = synth.make_problem(300, 12, 6, spectrum="dft", seed=31, real=True)
+    ld = p.N + 3
+    Abig = np.full((ld, p.N), np.nan)
+    Abig[: p.N] = p.A
+    Vbig = np.full((ld, p.ne), 5.0)
+    Vbig[: p.N] = p.V0
+    prm = L.default_params(nev=p.nev, nex=p.nex)
+    h = L.chase_create_real(p.N, prm)
+    try:
+        Ad, Vd, Sd = cm(Abig), cm(Vbig), cm(p.starts)
+        ritz, resid, st = L.chase_solve_real(h, L.dptr(Ad), ld, L.dptr(Vd), ld, 1, L.dptr(Sd), p.N, 4, p.nev,
+                                             sp())
+    finally:
+        L.chase_destroy(h)
+    assert st.status == 0
+    got = un(Vd)
+    assert np.all(got[p.N:] == 5.0)                      # padding rows untouched
+    ref_ritz, ref_resid, X, info = solve_real(p)
+    assert np.max(np.abs(np.array(ritz) - ref_ritz)) <= 1e-12 * p.norm2
+    check_real_solution(p, np.array(ritz), np.array(resid), got[: p.N, : p.nev])
