@@ -575,6 +575,7 @@ static int gram(Workspace& w, const z64* X, int64_t ldx, int64_t n, hipStream_t 
   g.A = X; g.lda = ldx;
   g.B = X; g.ldb = ldx;
   g.Y = w.G; g.ldy = n;
+  g.real_out = w.real;  // row-pair view: X^T X is the real part
   // lower triangle only: the Cholesky factorisation and the shift read nothing else
   const int splits = choose_splits(n, n, w.N, w.max_splits, true);
   return zgemm_splitk(1, 0, g, w.ws, splits, w.real ? 3 : 2, s);
@@ -607,6 +608,7 @@ static int chol_apply(Workspace& w, z64* X, int64_t ldx, int64_t n, bool shifted
   g.B = w.L; g.ldb = n;
   g.Y = w.B; g.ldy = w.N;
   g.upper_b = 1;
+  g.real_b = w.real;  // L^{-H} of a real Gram matrix is real-valued
   st = zgemm_launch(0, 1, g, s);
   if (st) return st;
   return copy_columns(w.B, w.N, X, ldx, w.N, n, s);
@@ -723,6 +725,7 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   q.A = Q; q.lda = ldq;
   q.B = w.B; q.ldb = N;
   q.Y = w.G; q.ldy = n;
+  q.real_out = w.real;
   st = zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits, true), w.real ? 3 : 2, s);
   if (st) return st;
   rocblas_set_stream(w.rb, s);
@@ -749,6 +752,7 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   b.A = Q; b.lda = ldq;
   b.B = w.G; b.ldb = n;
   b.Y = V; b.ldy = ldv;
+  b.real_b = w.real;  // eigenvectors of the real quotient
   st = zgemm_launch(0, 0, b, s);
   if (st) return st;
   GemmArgs hv;  // Q <- (H Q) W = H V
@@ -756,6 +760,7 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   hv.A = w.B; hv.lda = N;
   hv.B = w.G; hv.ldb = n;
   hv.Y = Q; hv.ldy = ldq;
+  hv.real_b = w.real;
   st = zgemm_launch(0, 0, hv, s);
   if (st) return st;
   st = residual_norms(Q, ldq, V, ldv, w.theta, N, n, w.resd, s);

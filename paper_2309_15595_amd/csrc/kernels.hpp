@@ -17,6 +17,8 @@ struct GemmArgs {
   const double* bscale = nullptr;  // optional: opB(B)[k][n] *= bscale[k] (diag(g) X^H)
   int upper_b = 0;     // opB(B) upper triangular: skip its zero K range
   int lower_only = 0;  // skip tiles strictly above the diagonal (m < n everywhere)
+  int real_b = 0;      // zgemm_launch nn / nc: opB(B) is real-valued (its imaginary parts are not read)
+  int real_out = 0;    // zgemm cn (also split over K): only the real part is formed, the imaginary is zero
 };
 
 // opa/opb: 0 = as stored, 1 = conjugate transpose.

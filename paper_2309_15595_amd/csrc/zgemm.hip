@@ -121,7 +121,11 @@ __device__ __forceinline__ bool map_tile(int64_t ntiles, int64_t tiles_n, int64_
   return true;
 }
 
-template <int OPA, int OPB>
+// MODE 0: the full complex product.  MODE 1 (real_b): opB(B) is real-valued,
+// so the products with its imaginary part are skipped.  MODE 2 (real_out):
+// only the real part of the product is wanted; the imaginary accumulators
+// are not formed (and are stored as zero).
+template <int OPA, int OPB, int MODE = 0>
 __device__ __forceinline__ void zgemm_body(const GemmArgs& g) {
   __shared__ double As[2][BK][APAD];
   __shared__ double Bs[2][BK][BPAD];
@@ -182,15 +186,19 @@ __device__ __forceinline__ void zgemm_body(const GemmArgs& g) {
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
           acc_re[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bre[nb], are[mb], acc_re[nb][mb], 0, 0, 0);
-          acc_im[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bre[nb], aim[mb], acc_im[nb][mb], 0, 0, 0);
+          if (MODE != 2)
+            acc_im[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bre[nb], aim[mb], acc_im[nb][mb], 0, 0, 0);
         }
+      if (MODE != 1) {
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
+        for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          acc_re[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bim[nb], aim[mb], acc_re[nb][mb], 0, 0, 0);
-          acc_im[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bim[nb], are[mb], acc_im[nb][mb], 0, 0, 0);
-        }
+          for (int mb = 0; mb < 4; ++mb) {
+            acc_re[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bim[nb], aim[mb], acc_re[nb][mb], 0, 0, 0);
+            if (MODE != 2)
+              acc_im[nb][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bim[nb], are[mb], acc_im[nb][mb], 0, 0, 0);
+          }
+      }
     }
   }
 
@@ -231,6 +239,11 @@ __device__ __forceinline__ void zgemm_body(const GemmArgs& g) {
 __global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_nn(GemmArgs g) { zgemm_body<0, 0>(g); }
 __global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_cn(GemmArgs g) { zgemm_body<1, 0>(g); }
 __global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_nc(GemmArgs g) { zgemm_body<0, 1>(g); }
+// the real symmetric variant's products (row-pair view): real-valued small
+// right operands, and real parts of products of two real blocks
+__global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_nn_rb(GemmArgs g) { zgemm_body<0, 0, 1>(g); }
+__global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_nc_rb(GemmArgs g) { zgemm_body<0, 1, 1>(g); }
+__global__ __launch_bounds__(NT, ZGEMM_WAVES) void zgemm_cn_ro(GemmArgs g) { zgemm_body<1, 0, 2>(g); }
 
 // Sum of split-K partials (fixed order), optionally Hermitised, written to Y
 // with the epilogue alpha * S + beta * Y.
@@ -279,11 +292,14 @@ int zgemm_launch(int opa, int opb, const GemmArgs& g_in, hipStream_t stream) {
   }
   g.ws = nullptr;
   if (opa == 0 && opb == 0) {
-    hipLaunchKernelGGL(zgemm_nn, blocks, dim3(NT), 0, stream, g);
+    if (g.real_b) hipLaunchKernelGGL(zgemm_nn_rb, blocks, dim3(NT), 0, stream, g);
+    else hipLaunchKernelGGL(zgemm_nn, blocks, dim3(NT), 0, stream, g);
   } else if (opa == 1 && opb == 0) {
-    hipLaunchKernelGGL(zgemm_cn, blocks, dim3(NT), 0, stream, g);
+    if (g.real_out) hipLaunchKernelGGL(zgemm_cn_ro, blocks, dim3(NT), 0, stream, g);
+    else hipLaunchKernelGGL(zgemm_cn, blocks, dim3(NT), 0, stream, g);
   } else if (opa == 0 && opb == 1) {
-    hipLaunchKernelGGL(zgemm_nc, blocks, dim3(NT), 0, stream, g);
+    if (g.real_b) hipLaunchKernelGGL(zgemm_nc_rb, blocks, dim3(NT), 0, stream, g);
+    else hipLaunchKernelGGL(zgemm_nc, blocks, dim3(NT), 0, stream, g);
   } else {
     return -1;
   }
@@ -324,11 +340,14 @@ int zgemm_splitk(int opa, int opb, const GemmArgs& g_in, void* ws, int splits, i
   const int64_t tiles = cdiv(g.M, BM) * cdiv(g.N, BN);
   dim3 blocks((unsigned)(8 * cdiv(tiles, 8)), (unsigned)splits, 1);
   if (opa == 1 && opb == 0) {
-    hipLaunchKernelGGL(zgemm_cn, blocks, dim3(NT), 0, stream, g);
+    if (g.real_out) hipLaunchKernelGGL(zgemm_cn_ro, blocks, dim3(NT), 0, stream, g);
+    else hipLaunchKernelGGL(zgemm_cn, blocks, dim3(NT), 0, stream, g);
   } else if (opa == 0 && opb == 0) {
-    hipLaunchKernelGGL(zgemm_nn, blocks, dim3(NT), 0, stream, g);
+    if (g.real_b) hipLaunchKernelGGL(zgemm_nn_rb, blocks, dim3(NT), 0, stream, g);
+    else hipLaunchKernelGGL(zgemm_nn, blocks, dim3(NT), 0, stream, g);
   } else if (opa == 0 && opb == 1) {
-    hipLaunchKernelGGL(zgemm_nc, blocks, dim3(NT), 0, stream, g);
+    if (g.real_b) hipLaunchKernelGGL(zgemm_nc_rb, blocks, dim3(NT), 0, stream, g);
+    else hipLaunchKernelGGL(zgemm_nc, blocks, dim3(NT), 0, stream, g);
   } else {
     return -1;
   }
