@@ -219,3 +219,22 @@ def test_real_solve_odd_leading_dimension(L):
     ref_ritz, ref_resid, X, info = solve_real(p)
     assert np.max(np.abs(np.array(ritz) - ref_ritz)) <= 1e-12 * p.norm2
     check_real_solution(p, np.array(ritz), np.array(resid), got[: p.N, : p.nev])
+
+
+@pytest.mark.parametrize("N,nev,nex", [(5, 1, 1), (16, 2, 2), (17, 3, 1), (64, 1, 0)])
+def test_real_tiny_orders(L, N, nev, nex):
+    """Degenerate sizes: one-tile problems, odd orders (one padding row), a
+    single wanted pair, and nex = 0, where the damped interval starts at the
+    wanted eigenvalue itself and the method (oracle alike) does not reach
+    tol within MaxIter: the outcome must be the oracle's."""
+    p = synth.make_problem(N, nev, nex, spectrum="uniform", seed=100 + N, real=True)
+    ritz, resid, X, info = solve_real(p)
+    r = oc.chase(p.A, oc.Params(nev=nev, nex=nex), V0=p.V0, starts=p.starts)
+    assert info.converged == r.converged, (info.stats, r.converged)
+    if r.converged:
+        check_real_solution(p, ritz, resid, X)
+        assert np.max(np.abs(ritz - r.evals)) <= 1e-10 * p.norm2
+    else:
+        assert info.status == 1 and info.stats["iterations"] == r.iterations
+        assert np.max(np.abs(ritz - r.evals)) <= 1e-8 * p.norm2
+        assert np.max(resid) <= 10 * np.max(r.resid)
