@@ -20,6 +20,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -1780,6 +1781,13 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
       // The rest of the iteration is per problem and latency-bound (small
       // kernels, the eigensolve, host decisions): overlap problems on
       // worker threads, each with its own stream after the grouped filter.
+      // Workers take the active problems from a shared queue, largest first,
+      // so that uneven orders spread evenly over the workers.
+      std::vector<int> order;
+      for (int i = 0; i < count; ++i)
+        if (ps[i].active()) order.push_back(i);
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ps[x].N * ps[x].na() > ps[y].N * ps[y].na(); });
+      std::atomic<size_t> next{0};
       std::vector<int> wst(nw, kOk);
       std::vector<std::thread> pool;
       for (int wk = 0; wk < nw; ++wk)
@@ -1788,8 +1796,8 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
             wst[wk] = kHipError;
             return;
           }
-          for (int i = wk; i < count; i += nw)
-            if (ps[i].active() && (wst[wk] = ps[i].post_filter(wstreams[wk]))) return;
+          for (size_t q; (q = next.fetch_add(1)) < order.size();)
+            if ((wst[wk] = ps[order[q]].post_filter(wstreams[wk]))) return;
         });
       for (auto& th : pool) th.join();
       for (int wk = 0; wk < nw; ++wk)
