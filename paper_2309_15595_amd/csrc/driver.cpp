@@ -692,8 +692,9 @@ static int caqr(Workspace& w, z64* X, int64_t ldx, int64_t n, double cond, int f
 // copy of them, theta/resd (device) the Ritz values and residual norms.
 // HC = H Q is computed once (Alg. 2's H C); the residual's H V is formed as
 // (H Q) W, the same product reassociated.
-static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_t ldq, z64* V, int64_t ldv,
-                         int64_t n, hipStream_t s) {
+// The three parts of rayleigh_ritz: the projection (B = H Q, G = Q^H B),
+// the n x n eigensolve (W into G, theta) and the rest.
+static int rr_project(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_t ldq, int64_t n, hipStream_t s) {
   if (n <= 0) return kOk;
   const int64_t N = w.N;
   GemmArgs g;  // B = H Q
@@ -727,8 +728,12 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   q.B = w.B; q.ldb = N;
   q.Y = w.G; q.ldy = n;
   q.real_out = w.real;
-  st = zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits, true), w.real ? 3 : 2, s);
-  if (st) return st;
+  return zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits, true), w.real ? 3 : 2, s);
+}
+
+static int rr_eigensolve(Workspace& w, int64_t n, hipStream_t s) {
+  if (n <= 0) return kOk;
+  int st;
   rocblas_set_stream(w.rb, s);
   if (w.real) {  // real symmetric quotient: eigenvectors real, back in complex storage
     if ((st = z_real_part(w.G, n, w.Gr, n, n, s))) return st;
@@ -748,6 +753,13 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
       return kHipError;
     }
   }
+  return kOk;
+}
+
+static int rr_finish(Workspace& w, z64* Q, int64_t ldq, z64* V, int64_t ldv, int64_t n, hipStream_t s) {
+  if (n <= 0) return kOk;
+  const int64_t N = w.N;
+  int st;
   GemmArgs b;  // V = Q W
   b.M = N; b.N = n; b.K = n;
   b.A = Q; b.lda = ldq;
@@ -767,6 +779,13 @@ static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_
   st = residual_norms(Q, ldq, V, ldv, w.theta, N, n, w.resd, s);
   if (st) return st;
   return copy_columns(V, ldv, Q, ldq, N, n, s);
+}
+
+static int rayleigh_ritz(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_t ldq, z64* V, int64_t ldv,
+                         int64_t n, hipStream_t s) {
+  int st;
+  if ((st = rr_project(w, A, lda, Q, ldq, n, s)) || (st = rr_eigensolve(w, n, s))) return st;
+  return rr_finish(w, Q, ldq, V, ldv, n, s);
 }
 
 static int lanczos(Workspace& w, const z64* A, int64_t lda, const z64* starts, int64_t lds, int nstarts,
@@ -1149,11 +1168,22 @@ struct ProblemState {
 
   // CondEst, 1D-CAQR, restore/save, Rayleigh-Ritz, residuals, locking.
   int post_filter(hipStream_t s) {
+    int st;
+    if ((st = post_filter_a(s)) || (st = rr_eigensolve(*w, na(), s))) return st;
+    return post_filter_b(s);
+  }
+
+  // The part of post_filter up to the Rayleigh-Ritz projection (the n_a x n_a
+  // quotient in w->G), and the part after its eigensolve.
+  double acc0[3] = {0, 0, 0};  // phase timers when the iteration's trace record began
+  int post_filter_a(hipStream_t s) {
     int st = kOk;
     std::vector<double> Lam_est = Lam;
     if (it == 1) std::fill(Lam_est.begin(), Lam_est.end(), mu1_cur);
     const double cond = cond_est(Lam_est.data(), c, e, degs.data(), ne, locked);
-    const double acc0[3] = {t_f.acc, t_qr.acc, t_rr.acc};
+    acc0[0] = t_f.acc;
+    acc0[1] = t_qr.acc;
+    acc0[2] = t_rr.acc;
     if (trace_level > 0) {
       rec = chase_trace_t{};
       rec.iteration = it;
@@ -1174,14 +1204,19 @@ struct ProblemState {
     if ((st = caqr(*w, V, ldv, ne, cond, P.force_qr, &variant, s))) return st;
     t_qr.stop(s);
     S.qr_count[variant] += 1;
+    rec.qr_variant = variant;
 
     // restore the locked columns, save the new active ones
     if (locked > 0 && (st = copy_columns(w->C2, N, V, ldv, N, locked, s))) return st;
     if ((st = copy_columns(V + (int64_t)locked * ldv, ldv, w->C2 + (int64_t)locked * N, N, N, na(), s))) return st;
 
     t_rr.start(s);
-    if ((st = rayleigh_ritz(*w, A, lda, w->C2 + (int64_t)locked * N, N, V + (int64_t)locked * ldv, ldv, na(), s)))
-      return st;
+    return rr_project(*w, A, lda, w->C2 + (int64_t)locked * N, N, na(), s);
+  }
+
+  int post_filter_b(hipStream_t s) {
+    int st;
+    if ((st = rr_finish(*w, w->C2 + (int64_t)locked * N, N, V + (int64_t)locked * ldv, ldv, na(), s))) return st;
     t_rr.stop(s);
     total_mv += 2 * (int64_t)na();
     CHASE_CHK(hipMemcpyAsync(th_h.data(), w->theta, na() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1189,7 +1224,6 @@ struct ProblemState {
     CHASE_CHK(hipStreamSynchronize(s));
     collect_timers();
     if (trace_level > 0 && trace && trace->size() < CHASE_TRACE_MAX) {
-      rec.qr_variant = variant;
       rec.t_filter = t_f.acc - acc0[0];  // the filter's events are collected here
       rec.t_qr = t_qr.acc - acc0[1];
       rec.t_rr = t_rr.acc - acc0[2];
@@ -1779,10 +1813,10 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
       t_f.stop(s);
       CHASE_CHK(hipEventRecord(filtered, s));
       // The rest of the iteration is per problem and latency-bound (small
-      // kernels, the eigensolve, host decisions): overlap problems on
-      // worker threads, each with its own stream after the grouped filter.
-      // Workers take the active problems from a shared queue, largest first,
-      // so that uneven orders spread evenly over the workers.
+      // kernels, the eigensolve, host decisions): overlap problems on worker
+      // threads, each with its own stream after the grouped filter.  Workers
+      // take the active problems from a shared queue, largest first, so that
+      // uneven orders spread evenly over the workers.
       std::vector<int> order;
       for (int i = 0; i < count; ++i)
         if (ps[i].active()) order.push_back(i);
