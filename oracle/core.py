@@ -236,7 +236,11 @@ def cond_est(Lam: np.ndarray, c: float, e: float, degs: np.ndarray,
     t_active = (Lam[locked] - c) / e
     d = int(degs[locked])
     d_max = int(np.max(degs[locked:]))
-    return rho(t_active) ** d * rho(t_first) ** (d_max - d)
+    # IEEE product: an estimate beyond the double range is +inf, which takes
+    # the same branch of Alg. 4 as any other estimate above its threshold.
+    with np.errstate(over="ignore"):
+        est = np.float64(rho(t_active)) ** d * np.float64(rho(t_first)) ** (d_max - d)
+    return float(est)
 
 
 def select_qr(cond: float) -> int:

@@ -509,18 +509,52 @@ static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, in
   return kOk;
 }
 
+// log T_k(tau) for tau >= 1, where T_k(tau) = (r^k + r^-k) / 2 with
+// r = tau + sqrt(tau^2 - 1); 0 for tau < 1 (|T_k| <= 1 there).  Written so
+// that neither r^k nor tau^2 is formed.
+static double log_cheb(int k, double tau) {
+  if (!(tau > 1.0)) return 0.0;
+  const double q = 1.0 / tau;
+  const double lr = std::log(tau) + std::log1p(std::sqrt((1.0 - q) * (1.0 + q)));
+  return k * lr + std::log1p(std::exp(-2.0 * k * lr)) - std::log(2.0);
+}
+
+// Power-of-two range guard of the low-precision recurrence.  The filter is
+// normalised at mu1, but mu1 is the smallest Ritz value of the last
+// iteration, so eigenvalues below it grow like T_k(t(lambda)) / T_k(t(mu1)),
+// which can pass the FP32 range (about 2^128) long before the FP64 one when
+// the Ritz values are still far from the spectrum (tiny orders, poor
+// starts).  Step k stores 2^-m[k] X_k instead of X_k, with m[k] chosen from
+// the bound T_k(t(lam_lo)) / T_k(t(mu1)) so that the stored iterate stays
+// below 2^90; the recurrence is linear and homogeneous in (X_k, X_{k-1}), so
+// the scalars of each step absorb the ratios and the widening conversion
+// multiplies the finished column by 2^m[d] in FP64.  m is zero whenever the
+// bound stays below 2^90, which leaves every scalar and value unchanged.
+static std::vector<int> lowp_range_exponents(int dmax, double c, double e, double mu1, double lam_lo) {
+  std::vector<int> m((size_t)dmax + 1, 0);
+  const double tau_lo = std::fabs((lam_lo - c) / e), tau_mu = std::fabs((mu1 - c) / e);
+  if (!std::isfinite(tau_lo) || !std::isfinite(tau_mu)) return m;
+  for (int k = 1; k <= dmax; ++k) {
+    const double log2_growth = (log_cheb(k, tau_lo) - log_cheb(k, tau_mu)) / std::log(2.0);
+    m[k] = std::max(0, (int)std::ceil(log2_growth - 90.0));
+  }
+  return m;
+}
+
 // Low-precision filter for the columns still on an FP32 or BF16x3 rung: the
 // same recurrence and scalars as plan_filter, on complex64 copies of the
 // columns (X0/X1 ping-pong), converted back to complex128 as each column
 // reaches its degree.  `launch` runs one step's GEMM; it is told which buffer
-// the step reads and the step's first column.
+// the step reads and the step's first column.  lam_lo: a lower estimate of
+// the spectrum for the range guard above.
 static int run_filter_lowp(int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int64_t n, const int32_t* degs,
-                           double c, double e, double mu1, int64_t* matvecs, int64_t* launches, hipStream_t s,
-                           const std::function<int(const CGemmArgs&, bool, int64_t)>& launch) {
+                           double c, double e, double mu1, double lam_lo, int64_t* matvecs, int64_t* launches,
+                           hipStream_t s, const std::function<int(const CGemmArgs&, bool, int64_t)>& launch) {
   if (n <= 0) return kOk;
   int st = convert_z_to_c(V, ldv, X0, N, N, n, s);
   if (st) return st;
   const int dmax = degs[n - 1];
+  const std::vector<int> m = lowp_range_exponents(dmax, c, e, mu1, lam_lo);
   int64_t mv = 0, nl = 0;
   const double sigma1 = e / (mu1 - c);
   double sigma = sigma1;
@@ -530,7 +564,7 @@ static int run_filter_lowp(int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int
     while (s0 < n && degs[s0] < k + 1) ++s0;
     // columns that finished after step k (degree == k, even) sit in X0
     if (s0 > done) {
-      st = convert_c_to_z(X0 + done * N, N, V + done * ldv, ldv, N, s0 - done, s);
+      st = convert_c_to_z(X0 + done * N, N, V + done * ldv, ldv, N, s0 - done, s, std::ldexp(1.0, m[k]));
       if (st) return st;
       done = s0;
     }
@@ -546,6 +580,10 @@ static int run_filter_lowp(int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int
       beta = -sigma * sigma_next;
       sigma = sigma_next;
     }
+    // stored iterates carry 2^-m[k]: X_{k+1} from X_k scales by 2^(m[k]-m[k+1]),
+    // the X_{k-1} term by 2^(m[k-1]-m[k+1])
+    alpha = std::ldexp(alpha, m[k] - m[k + 1]);
+    if (k > 0) beta = std::ldexp(beta, m[k - 1] - m[k + 1]);
     const bool cur0 = (k % 2 == 0);
     c32* cur = cur0 ? X0 : X1;
     c32* out = cur0 ? X1 : X0;
@@ -561,7 +599,7 @@ static int run_filter_lowp(int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int
     ++nl;
   }
   if (n > done) {
-    st = convert_c_to_z(X0 + done * N, N, V + done * ldv, ldv, N, n - done, s);
+    st = convert_c_to_z(X0 + done * N, N, V + done * ldv, ldv, N, n - done, s, std::ldexp(1.0, m[dmax]));
     if (st) return st;
   }
   if (matvecs) *matvecs = mv;
@@ -1077,6 +1115,13 @@ struct ProblemState {
   }
   int n_low() const { return n_rung(1) + n_rung(2); }
 
+  // Lower estimate of the spectrum for the low-precision range guard: the
+  // smaller of the Lanczos estimate and the current mu1, less 1% of the span.
+  double lam_lo() const {
+    const double lo = std::min(bnd[1], mu1_cur);
+    return lo - 0.01 * std::fabs(b_sup - lo);
+  }
+
   // FP64 filter GEMMs of this iteration (the columns not in FP32).
   std::vector<GemmArgs> plan() {
     const int nl = mixed ? n_low() : 0;
@@ -1121,7 +1166,7 @@ struct ProblemState {
         return bfilter_launch(b, s, tw, tc);
       };
       if ((st = run_filter_lowp(N, V + (int64_t)locked * ldv, ldv, w->X32a, w->X32b, n16, degs.data() + locked,
-                                c, e, mu1_cur, &mv16, &nl16, s, launch)))
+                                c, e, mu1_cur, lam_lo(), &mv16, &nl16, s, launch)))
         return st;
       S.filter_matvecs_bf16 += mv16;
       mv += mv16;
@@ -1140,7 +1185,7 @@ struct ProblemState {
         return cfilter_big_launch(b, s, tw, tc);
       };
       if ((st = run_filter_lowp(N, V + (int64_t)(locked + n16) * ldv, ldv, w->X32a, w->X32b, n32,
-                                degs.data() + locked + n16, c, e, mu1_cur, &mv32, &nl32, s, launch)))
+                                degs.data() + locked + n16, c, e, mu1_cur, lam_lo(), &mv32, &nl32, s, launch)))
         return st;
       S.filter_matvecs_fp32 += mv32;
       mv += mv32;

@@ -222,10 +222,11 @@ int dcopy_pad(const double* src, int64_t lds, int64_t rows_src, int64_t cols_src
 // R = Re(G) and G = R + 0 i for n x n blocks.
 int z_real_part(const z64* G, int64_t ldg, double* R, int64_t ldr, int64_t n, hipStream_t s);
 int d_to_z(const double* R, int64_t ldr, z64* G, int64_t ldg, int64_t n, hipStream_t s);
-// complex128 <-> complex64 conversions (column blocks).
+// complex128 <-> complex64 conversions (column blocks); the widening one
+// multiplies by `scale` in FP64 (1 leaves the values as they are).
 int convert_z_to_c(const z64* src, int64_t lds, c32* dst, int64_t ldd, int64_t N, int64_t n,
                    hipStream_t s);
 int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N, int64_t n,
-                   hipStream_t s);
+                   hipStream_t s, double scale = 1.0);
 
 }  // namespace chase

@@ -244,12 +244,12 @@ __global__ void z2c_kernel(const zv* src, int64_t lds, c32* dst, int64_t ldd, in
   dst[m + j * ldd] = c32{(float)v.re, (float)v.im};
 }
 
-__global__ void c2z_kernel(const c32* src, int64_t lds, zv* dst, int64_t ldd, int64_t N) {
+__global__ void c2z_kernel(const c32* src, int64_t lds, zv* dst, int64_t ldd, int64_t N, double scale) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (m >= N) return;
   c32 v = src[m + j * lds];
-  dst[m + j * ldd] = zv{(double)v.re, (double)v.im};
+  dst[m + j * ldd] = zv{(double)v.re * scale, (double)v.im * scale};
 }
 
 // ---- Lanczos ----------------------------------------------------------------
@@ -624,10 +624,11 @@ int convert_z_to_c(const z64* src, int64_t lds, c32* dst, int64_t ldd, int64_t N
   return kOk;
 }
 
-int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N, int64_t n, hipStream_t s) {
+int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N, int64_t n, hipStream_t s,
+                   double scale) {
   if (n <= 0 || N <= 0) return kOk;
   hipLaunchKernelGGL(c2z_kernel, dim3((unsigned)cdiv(N, 256), (unsigned)n), dim3(256), 0, s, src, lds,
-                     reinterpret_cast<zv*>(dst), ldd, N);
+                     reinterpret_cast<zv*>(dst), ldd, N, scale);
   CHASE_CHK_LAUNCH();
   return kOk;
 }

@@ -130,6 +130,23 @@ def check_condest_golden(oc):
         assert abs(got - case["expected"]) <= 1e-12 * case["expected"], (case, got)
 
 
+def check_condest_overflow(oc):
+    """Alg. 5 far outside the damped interval: the growth factor
+    |t| + sqrt(t^2 - 1) for t = -2000 raised to d = 80 is finite (about 1e288,
+    checked in logarithms); to d = 200 it passes the double range and the
+    estimate is +inf, which still selects the shifted CholeskyQR of Alg. 4."""
+    ne = 3
+    Lam = np.array([-1.0, 0.0, 0.5])
+    c, e = 1.0, 1e-3                      # t = (lambda_1 - c) / e = -2000
+    g = 2000.0 + np.sqrt(2000.0 ** 2 - 1.0)
+    got = oc.cond_est(Lam, c, e, np.full(ne, 80, dtype=np.int64), 0)
+    assert np.isfinite(got)
+    assert abs(np.log(got) - 80 * np.log(g)) <= 1e-12 * 80 * np.log(g)
+    big = oc.cond_est(Lam, c, e, np.full(ne, 200, dtype=np.int64), 0)
+    assert big == np.inf
+    assert oc.select_qr(big) == oc.QR_SHIFTED
+
+
 def check_qr_selection(oc):
     consts = _golden("paper_constants.json")
     hi = consts["cond_shifted_threshold"]["value"]

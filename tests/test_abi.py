@@ -74,6 +74,8 @@ def test_cond_est_matches_oracle_golden():
         degs[-1] = case["d_max"]
         got = L.chase_cond_est(lam, case["c"], case["e"], degs, locked)
         assert abs(got - case["expected"]) <= 1e-12 * case["expected"]
+    # an estimate beyond the double range is +inf (the shifted branch)
+    assert L.chase_cond_est([-1.0, 0.0, 0.5], 1.0, 1e-3, [200, 200, 200], 0) == np.inf
 
 
 def test_invalid_arguments_rejected_on_host():

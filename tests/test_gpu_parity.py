@@ -237,6 +237,36 @@ def test_solve_ragged_sizes(L, N, nev, nex, spectrum):
     assert np.max(np.abs(ritz - r.evals)) <= 1e-10 * p.norm2
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("N,nev,nex", [(2, 1, 0), (3, 1, 1), (8, 2, 1), (17, 3, 2)])
+def test_solve_tiny_orders(L, N, nev, nex, prec):
+    """Orders below one tile: the whole search space is nearly all of C^N.
+    At N = 2 the first Ritz value lands far above the smallest eigenvalue, so
+    the next filter, normalised there, grows that eigenvector's component by
+    about 1e43: past the FP32 range, which the low-precision rungs must
+    absorb without a breakdown.  With nex = 0 the damped interval reaches
+    down to the wanted Ritz value, so once that value is accurate the filter
+    no longer separates the two eigenvalues: the FP64 oracle gets there in
+    one step from a poor Ritz value, while a low rung stops at FP32 accuracy
+    and the FP64 rung then stalls.  Those cases check the range guard only
+    (no breakdown, the FP32-accurate eigenvalue)."""
+    p = synth.make_problem(N, nev, nex, spectrum="uniform", basis="gaussian", seed=300 + N)
+    code = {"fp64": L.CHASE_FP64, "fp32": L.CHASE_FP32_MIXED, "bf16x3": L.CHASE_BF16X3_MIXED}[prec]
+    if prec != "fp64" and nex == 0:
+        from paper_2309_15595_amd.api import Solver
+        with Solver(p.N, p.nev, p.nex, precision=code, max_iter=4) as s:
+            ritz, resid, info = s.solve_colmajor(cm(p.A), cm(p.V0), True, cm(p.starts))
+        assert info.status in (0, 1), info.stats
+        assert info.stats["filter_matvecs_fp32"] + info.stats["filter_matvecs_bf16"] > 0
+        assert np.max(np.abs(ritz - p.lam[:nev])) <= 1e-6 * p.norm2
+        return
+    ritz, resid, X, info = solve_gpu(p, precision=code)
+    r = oc.chase(p.A, oc.Params(nev=nev, nex=nex), V0=p.V0, starts=p.starts)
+    assert info.converged == r.converged, info.stats
+    assert np.max(np.abs(ritz - r.evals)) <= 1e-10 * p.norm2
+    assert np.max(np.abs(ritz - p.lam[:nev])) <= 1e-10 * p.norm2
+
+
 @pytest.mark.parametrize("force", [0, 1, 2, 3])
 def test_solve_forced_qr_variants(L, force):
     p = synth.make_problem(400, 20, 10, spectrum="uniform", seed=11)

@@ -17,6 +17,7 @@ PINS = [
     pins.check_lanczos_bounds,
     pins.check_lanczos_full_spectrum,
     pins.check_condest_golden,
+    pins.check_condest_overflow,
     pins.check_qr_selection,
     pins.check_shift_formula,
     pins.check_caqr_orthogonality,
