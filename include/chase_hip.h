@@ -108,6 +108,27 @@ int chase_default_params(chase_params_t* p);
  * Returns 2 when an allocation fails (nothing is leaked). */
 int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h);
 
+/* Device bytes that creating a handle for order N and these params
+ * allocates, computed on the host by the same code path that allocates
+ * (nothing is allocated and no device call is made; no GPU is needed).
+ * This is the library's share of Eq. (2)'s memory model at p = q = 1
+ * (N^2 + 4 N n_e + n_e^2 words): the caller holds H and V (N^2 + N n_e
+ * words); the library holds C2 and B (2 N n_e words), three n_e x n_e
+ * matrices and the 16 split-K partials of the n_e x n_e products
+ * (19 n_e^2 words), a fixed 256 MiB of split-K tail partials for the filter,
+ * O(N + n_e) Lanczos, Householder-panel and scalar vectors, and the
+ * low-precision copies listed under chase_create.
+ *   variant  0: chase_create (complex128), 1: chase_create_real (float64;
+ *            an odd N includes the zero-padded copy of H that every solve
+ *            of an odd order uses; an odd lda at even N adds the same
+ *            (N+1)^2 doubles on first use), 2: chase_create_c64
+ *   bytes    (host) out
+ * Not counted: the rocBLAS handle's own device-memory pool, which rocSOLVER's
+ * eigensolver and QR calls grow on demand (of order n_e^2 words).
+ * Returns -1 for N < 2, -2 for invalid params (or a precision the variant
+ * does not offer), -3 for an unknown variant, -4 for a null bytes. */
+int chase_workspace_bytes(int64_t N, const chase_params_t* p, int32_t variant, int64_t* bytes);
+
 /* Solves for the nev lowest eigenpairs of Hermitian H (Alg. 2).
  *   A      (device) N x N, full Hermitian storage, read only
  *   V      (device) N x (nev+nex), in/out.  On entry the initial block when

@@ -74,6 +74,7 @@ _I64P = C.POINTER(C.c_int64)
 SIGNATURES = {
     "chase_default_params": (C.c_int, [C.POINTER(chase_params_t)]),
     "chase_create": (C.c_int, [_I64, C.POINTER(chase_params_t), C.POINTER(_P)]),
+    "chase_workspace_bytes": (C.c_int, [_I64, C.POINTER(chase_params_t), _I32, C.POINTER(_I64)]),
     "chase_solve": (C.c_int, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _I32, _DP, _DP,
                               C.POINTER(chase_stats_t), _P]),
     "chase_destroy": (C.c_int, [_P]),
@@ -184,6 +185,13 @@ def chase_solve_real(h, A_ptr, lda, V_ptr, ldv, use_v0, starts_ptr, ld_starts, n
                                  nstarts, ritz, resid, C.byref(stats), stream)
     check(st, "chase_solve_real", allow_not_converged=True)
     return list(ritz), list(resid), stats
+
+
+def chase_workspace_bytes(N: int, params: chase_params_t, variant: int = 0) -> int:
+    """Device bytes a handle of this order and params allocates (host only)."""
+    out = _I64(0)
+    check(load().chase_workspace_bytes(N, C.byref(params), variant, C.byref(out)), "chase_workspace_bytes")
+    return out.value
 
 
 def chase_create_c64(N: int, params: chase_params_t):

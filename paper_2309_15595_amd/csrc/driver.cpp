@@ -255,11 +255,20 @@ struct Workspace {
   int64_t ldh32 = 0;
   rocblas_handle rb = nullptr;
   std::vector<void*> owned;
+  // Sizing mode: alloc adds up the bytes and allocates nothing; create()
+  // then makes no device call either.
+  bool counting = false;
+  size_t counted = 0;
 
   template <class T>
   int alloc(T** p, size_t count) {
     void* q = nullptr;
     if (count == 0) count = 1;
+    if (counting) {
+      counted += count * sizeof(T);
+      *p = nullptr;
+      return kOk;
+    }
     if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
       set_msg("hipMalloc failed");
@@ -299,8 +308,8 @@ struct Workspace {
     st = st ? st : alloc(&perm, (size_t)ne);
     st = st ? st : alloc(reinterpret_cast<char**>(&tail_ws), (size_t)tail_workspace_bytes());
     st = st ? st : alloc(&tail_counters, (size_t)kTailCounterInts);
-    if (!st) st = tail_counters_init(tail_counters, nullptr);
-    if (!st && hipDeviceSynchronize() != hipSuccess) st = kHipError;
+    if (!st && !counting) st = tail_counters_init(tail_counters, nullptr);
+    if (!st && !counting && hipDeviceSynchronize() != hipSuccess) st = kHipError;
     st = st ? st : alloc(&lz_alpha, 8 * 256);
     st = st ? st : alloc(&lz_beta, 8 * 256);
     if (lanczos) {
@@ -319,13 +328,13 @@ struct Workspace {
       st = st ? st : alloc(&P16, (size_t)4 * ldp * N);
       st = st ? st : alloc(&XP16a, (size_t)4 * ldp * ne);
       st = st ? st : alloc(&XP16b, (size_t)4 * ldp * ne);
-      if (!st && (hipMemset(XP16a, 0, sizeof(uint16_t) * 4 * ldp * ne) != hipSuccess ||
+      if (!st && !counting && (hipMemset(XP16a, 0, sizeof(uint16_t) * 4 * ldp * ne) != hipSuccess ||
                   hipMemset(XP16b, 0, sizeof(uint16_t) * 4 * ldp * ne) != hipSuccess)) {
         set_msg("hipMemset failed");
         st = kHipError;
       }
     }
-    if (!st && rocblas_create_handle(&rb) != rocblas_status_success) {
+    if (!st && !counting && rocblas_create_handle(&rb) != rocblas_status_success) {
       set_msg("rocblas_create_handle failed");
       st = kHipError;
     }
@@ -1408,6 +1417,30 @@ int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h) {
     return st;
   }
   *h = hh;
+  return kOk;
+}
+
+int chase_workspace_bytes(int64_t N, const chase_params_t* p, int32_t variant, int64_t* bytes) {
+  if (N < 2) return -1;
+  if (!valid_params(p) || (int64_t)p->nev + p->nex >= N) return -2;
+  if (variant < 0 || variant > 2) return -3;
+  if (!bytes) return -4;
+  if (variant == 1 && p->precision != CHASE_FP64) return -2;
+  if (variant == 2 && p->precision == CHASE_BF16X3_MIXED) return -2;
+  Workspace w;
+  w.counting = true;
+  const int ne = p->nev + p->nex;
+  int st;
+  if (variant == 0) {
+    st = w.create(N, ne, p->precision != CHASE_FP64, true, p->precision == CHASE_BF16X3_MIXED);
+  } else if (variant == 1) {
+    st = w.create_real(N, ne);
+    if (!st && N % 2 != 0) st = w.ensure_hpad();  // an odd order always solves on a padded copy of H
+  } else {
+    st = w.create_c64(N, ne);
+  }
+  if (st) return st;
+  *bytes = (int64_t)w.counted;
   return kOk;
 }
 

@@ -78,6 +78,48 @@ def test_cond_est_matches_oracle_golden():
     assert L.chase_cond_est([-1.0, 0.0, 0.5], 1.0, 1e-3, [200, 200, 200], 0) == np.inf
 
 
+def test_workspace_bytes_memory_model():
+    """Eq. (2) at p = q = 1 on the host, with no device call.  Eq. (2) counts
+    N^2 + 4 N n_e + n_e^2 words; the caller holds H and V (N^2 + N n_e), the
+    library C2 and B (2 N n_e), three n_e x n_e matrices plus the 16 split-K
+    partials of the n_e x n_e products (19 n_e^2), a fixed 256 MiB of filter
+    split-K tail partials and O(N + n_e) vectors.  Each option adds exactly
+    what it documents."""
+    L = _lib()
+    lib = L.load()
+    z = 16
+    tail = 256 << 20
+    for N, nev, nex in [(20000, 1000, 300), (5000, 200, 60), (1201, 90, 30)]:
+        ne = nev + nex
+        fp64 = L.chase_workspace_bytes(N, L.default_params(nev=nev, nex=nex), 0)
+        core = z * (2 * N * ne + 19 * ne * ne) + tail
+        assert core <= fp64 <= core + z * (64 * N + 128 * ne) + (1 << 20)
+        # one N x n_e block fewer than Eq. (2), 18 n_e^2 words and the tail more
+        eq2 = z * (N * N + 4 * N * ne + ne * ne)
+        assert z * (N * N + N * ne) + fp64 <= eq2 - z * N * ne + z * 18 * ne * ne + tail + z * (64 * N + 128 * ne) + (1 << 20)
+        fp32 = L.chase_workspace_bytes(N, L.default_params(nev=nev, nex=nex, precision=L.CHASE_FP32_MIXED), 0)
+        assert fp32 - fp64 == 8 * N * N + 2 * 8 * N * ne     # complex64 H and two complex64 blocks
+        bf16 = L.chase_workspace_bytes(N, L.default_params(nev=nev, nex=nex, precision=L.CHASE_BF16X3_MIXED), 0)
+        assert bf16 - fp32 >= 4 * 2 * N * N                  # four bfloat16 planes of H
+        c64 = L.chase_workspace_bytes(N, L.default_params(nev=nev, nex=nex), 2)
+        assert fp64 < c64 < fp32                             # FP32 blocks, no copy of H
+    # real variant: an odd order adds the zero-padded (N+1)^2 copy of H and
+    # otherwise sizes like the next even order (same row-pair workspace)
+    prm = L.default_params(nev=40, nex=20)
+    even = L.chase_workspace_bytes(1002, prm, 1)
+    odd = L.chase_workspace_bytes(1001, prm, 1)
+    assert odd - even == 8 * 1002 * 1002
+    assert even < L.chase_workspace_bytes(1002, prm, 0)
+    out = ctypes.c_int64(0)
+    assert lib.chase_workspace_bytes(1, ctypes.byref(prm), 0, ctypes.byref(out)) == -1
+    assert lib.chase_workspace_bytes(60, ctypes.byref(prm), 0, ctypes.byref(out)) == -2   # nev+nex >= N
+    assert lib.chase_workspace_bytes(1000, ctypes.byref(prm), 3, ctypes.byref(out)) == -3
+    assert lib.chase_workspace_bytes(1000, ctypes.byref(prm), 0, None) == -4
+    bf = L.default_params(nev=40, nex=20, precision=L.CHASE_BF16X3_MIXED)
+    assert lib.chase_workspace_bytes(1000, ctypes.byref(bf), 1, ctypes.byref(out)) == -2
+    assert lib.chase_workspace_bytes(1000, ctypes.byref(bf), 2, ctypes.byref(out)) == -2
+
+
 def test_invalid_arguments_rejected_on_host():
     """Argument checks run before any device call."""
     L = _lib()
