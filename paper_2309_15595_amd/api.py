@@ -41,6 +41,17 @@ class SolveInfo:
     stats: dict
 
 
+_VARIANTS = {torch.complex128: 0, torch.float64: 1, torch.complex64: 2}
+
+
+def workspace_bytes(N: int, nev: int, nex: int, *, dtype=torch.complex128, **params) -> int:
+    """Device bytes a Solver of these arguments allocates (host-side count;
+    H and the block are the caller's and not included)."""
+    if dtype not in _VARIANTS:
+        raise TypeError(f"unsupported dtype {dtype}")
+    return _lib.chase_workspace_bytes(N, _lib.default_params(nev=nev, nex=nex, **params), _VARIANTS[dtype])
+
+
 class Solver:
     """A chase_create/chase_destroy handle for problems of order N."""
 

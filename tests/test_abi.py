@@ -115,6 +115,9 @@ def test_workspace_bytes_memory_model():
     assert lib.chase_workspace_bytes(60, ctypes.byref(prm), 0, ctypes.byref(out)) == -2   # nev+nex >= N
     assert lib.chase_workspace_bytes(1000, ctypes.byref(prm), 3, ctypes.byref(out)) == -3
     assert lib.chase_workspace_bytes(1000, ctypes.byref(prm), 0, None) == -4
+    import torch
+    from paper_2309_15595_amd.api import workspace_bytes
+    assert workspace_bytes(1001, 40, 20, dtype=torch.float64) == odd
     bf = L.default_params(nev=40, nex=20, precision=L.CHASE_BF16X3_MIXED)
     assert lib.chase_workspace_bytes(1000, ctypes.byref(bf), 1, ctypes.byref(out)) == -2
     assert lib.chase_workspace_bytes(1000, ctypes.byref(bf), 2, ctypes.byref(out)) == -2
