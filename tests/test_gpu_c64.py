@@ -123,7 +123,7 @@ def test_c64_leading_dimension(L):
     assert np.max(np.abs(np.array(ritz) - p.lam[: p.nev])) <= 1e-6 * p.norm2
 
 
-@pytest.mark.parametrize("N,nev,nex", [(2, 1, 0), (3, 1, 1), (8, 1, 1), (9, 2, 2), (64, 1, 1)])
+@pytest.mark.parametrize("N,nev,nex", [(2, 1, 0), (3, 1, 1), (8, 1, 1), (9, 2, 2), (64, 1, 1), (64, 40, 23)])
 def test_c64_tiny_orders(L, N, nev, nex):
     p = synth.make_problem(N, nev, nex, spectrum="uniform", seed=200 + N)
     ritz, resid, X, info = solve_c64(p)

@@ -238,7 +238,7 @@ def test_solve_ragged_sizes(L, N, nev, nex, spectrum):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("N,nev,nex", [(2, 1, 0), (3, 1, 1), (8, 2, 1), (17, 3, 2)])
+@pytest.mark.parametrize("N,nev,nex", [(2, 1, 0), (3, 1, 1), (8, 2, 1), (17, 3, 2), (33, 20, 12), (64, 40, 23)])
 def test_solve_tiny_orders(L, N, nev, nex, prec):
     """Orders below one tile: the whole search space is nearly all of C^N.
     At N = 2 the first Ritz value lands far above the smallest eigenvalue, so

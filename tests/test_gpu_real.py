@@ -221,10 +221,11 @@ def test_real_solve_odd_leading_dimension(L):
     check_real_solution(p, np.array(ritz), np.array(resid), got[: p.N, : p.nev])
 
 
-@pytest.mark.parametrize("N,nev,nex", [(2, 1, 0), (3, 1, 1), (5, 1, 1), (16, 2, 2), (17, 3, 1), (64, 1, 0)])
+@pytest.mark.parametrize("N,nev,nex", [(2, 1, 0), (3, 1, 1), (5, 1, 1), (16, 2, 2), (17, 3, 1), (64, 1, 0),
+                                       (33, 20, 12), (64, 40, 23)])   # n_e = N - 1
 def test_real_tiny_orders(L, N, nev, nex):
     """Degenerate sizes: one-tile problems, odd orders (one padding row), a
-    single wanted pair, and nex = 0, where the damped interval starts at the
+    single wanted pair, a block of N - 1 columns, and nex = 0, where the damped interval starts at the
     wanted eigenvalue itself and the method (oracle alike) does not reach
     tol within MaxIter: the outcome must be the oracle's."""
     p = synth.make_problem(N, nev, nex, spectrum="uniform", seed=100 + N, real=True)
