@@ -185,7 +185,11 @@ def main():
                       "N": N, "nev": nev, "nex": nex, "deg": 20, "max_deg": 36, "tol": 1e-10},
            "time_to_solution_s": float(np.median(tts)),
            "phases_s": {k: st[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr")},
-           "parity": parity, "roofline": roofline}
+           "parity": parity, "roofline": roofline,
+           # device memory (Eq. 2 at p = q = 1): H and the block are the caller's
+           "memory_bytes": {"caller_H_and_V": 16 * (N * N + N * (nev + nex)),
+                            "library_fp64": L.chase_workspace_bytes(N, L.default_params(nev=nev, nex=nex), 0),
+                            "eq2_words_x16": 16 * (N * N + 4 * N * (nev + nex) + (nev + nex) ** 2)}}
 
     if not args.no_mixed:
         del solver
