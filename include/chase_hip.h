@@ -65,7 +65,7 @@ typedef struct {
   int32_t deg_extra;    /* margin added by degree optimisation (2) */
   int32_t max_iter;     /* MaxIter (25) */
   int32_t opt;          /* 1 = per-vector degree optimisation (1) */
-  int32_t precision;    /* CHASE_FP64 or CHASE_FP32_MIXED */
+  int32_t precision;    /* CHASE_FP64, CHASE_FP32_MIXED or CHASE_BF16X3_MIXED */
   int32_t lanczos_steps;/* steps per Lanczos run (25) */
   int32_t force_qr;     /* CHASE_QR_AUTO, or force one QR variant (testing) */
   int32_t bounds_given; /* 1 = skip Lanczos and use b_sup, mu_1, mu_ne, norm_est */

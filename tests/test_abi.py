@@ -164,3 +164,30 @@ def test_struct_sizes_match_c_compiler(tmp_path):
     assert int(out[0]) == ctypes.sizeof(L.chase_params_t)
     assert int(out[1]) == ctypes.sizeof(L.chase_stats_t)
     assert int(out[2]) == ctypes.sizeof(L.chase_trace_t)
+
+
+def _build_c_example(out_path):
+    """Compile and link tests/native/c_abi_solve.c (plain C99, no torch)
+    against the in-tree library with the host C compiler."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    if cc is None or not os.path.isdir(os.path.join(rocm, "include", "hip")):
+        pytest.skip("no host C compiler or HIP headers")
+    libdir = os.path.join(ROOT, "paper_2309_15595_amd")
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(rocm, "include"), "-D__HIP_PLATFORM_AMD__",
+           os.path.join(ROOT, "tests", "native", "c_abi_solve.c"), "-L", libdir, "-lchase_hip",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm", f"-Wl,-rpath,{libdir}",
+           f"-Wl,-rpath,{os.path.join(rocm, 'lib')}", "-o", str(out_path)]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return out_path
+
+
+def test_c_example_builds_against_the_abi(tmp_path):
+    """The header and the library serve a plain C caller: the example builds
+    warning-free with -Wall -Wextra and links against libchase_hip.so."""
+    _lib().load()
+    exe = _build_c_example(tmp_path / "c_abi_solve")
+    assert exe.exists()
