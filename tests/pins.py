@@ -147,6 +147,50 @@ def check_condest_overflow(oc):
     assert oc.select_qr(big) == oc.QR_SHIFTED
 
 
+def _growth(t):
+    """Growth rate of T_k at |t| >= 1 in closed form: |t| + sqrt(t^2 - 1)."""
+    a = abs(t)
+    return a + np.sqrt(a * a - 1.0)
+
+
+def check_degree_opt(oc):
+    """Per-vector degrees of Alg. 2: even, within [2, max_deg]; outside the
+    damped interval d - extra is the smallest exponent (up to the even
+    round-up) with resd * g^-(d - extra) <= tol, g the growth rate at
+    t = (lambda - c) / e; inside it, or for a non-finite residual, the cap;
+    an already converged residual takes the margin alone."""
+    c, e, tol, max_deg, extra = 0.5, 0.5, 1e-10, 36, 2
+    lam = np.array([-0.1, -0.3, -0.05, -0.8, 0.2, -0.02, -0.2])
+    resd = np.array([1e-3, 1e-6, 1e-8, 1e-2, 1e-3, np.inf, 5e-11])
+    d = oc.degree_opt(resd, lam, c, e, tol, max_deg, extra)
+    assert np.all(d % 2 == 0) and np.all((d >= 2) & (d <= max_deg)), d
+    checked = 0
+    for j in range(lam.shape[0]):
+        t = (lam[j] - c) / e
+        if abs(t) <= 1.0 or not np.isfinite(resd[j]):
+            assert d[j] == max_deg, (j, d[j])
+            continue
+        if resd[j] <= tol:
+            assert d[j] == max(2, extra + extra % 2), (j, d[j])
+            continue
+        g, k = _growth(t), int(d[j]) - extra
+        assert d[j] < max_deg
+        assert resd[j] * g ** (-k) <= tol * (1 + 1e-12), (j, d[j])
+        assert resd[j] * g ** (-(k - 2)) > tol, (j, d[j])
+        checked += 1
+    assert checked == 4
+
+
+def check_lock_order(oc):
+    """Locking in Alg. 2: among the first n_lockable active pairs, those
+    with resd <= tol move to the front in their order; the rest keep their
+    relative order; a converged pair past n_lockable does not lock."""
+    resd = np.array([5e-11, 2e-10, 1e-12, 3e-11, 1e-13, 1e-9])
+    perm, k = oc.lock_order(resd, 4, 1e-10)
+    assert k == 3
+    assert list(perm) == [0, 2, 3, 1, 4, 5]
+
+
 def check_qr_selection(oc):
     consts = _golden("paper_constants.json")
     hi = consts["cond_shifted_threshold"]["value"]

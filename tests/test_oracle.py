@@ -18,6 +18,8 @@ PINS = [
     pins.check_lanczos_full_spectrum,
     pins.check_condest_golden,
     pins.check_condest_overflow,
+    pins.check_degree_opt,
+    pins.check_lock_order,
     pins.check_qr_selection,
     pins.check_shift_formula,
     pins.check_caqr_orthogonality,
@@ -288,6 +290,29 @@ def _lanczos_missing_term(A, start, k):
     return np.array(alphas), np.array(betas)
 
 
+def _degree_floor(resd, Lam, c, e, tol_abs, max_deg, deg_extra):
+    out = []
+    for j in range(resd.shape[0]):
+        r = oc.rho((Lam[j] - c) / e)
+        if r <= 1.0 + 1e-12 or not np.isfinite(resd[j]):
+            d = max_deg
+        elif resd[j] <= tol_abs:
+            d = deg_extra
+        else:
+            d = int(np.floor(np.log(resd[j] / tol_abs) / np.log(r))) + deg_extra
+        d = min(max(d, 2), max_deg)
+        out.append(d + d % 2)
+    return np.array(out)
+
+
+def _degree_no_margin(resd, Lam, c, e, tol_abs, max_deg, deg_extra):
+    return oc.degree_opt(resd, Lam, c, e, tol_abs, max_deg, 0)
+
+
+def _lock_past_nev(resd_active, n_lockable, tol_abs):
+    return oc.lock_order(resd_active, resd_active.shape[0], tol_abs)
+
+
 def _grad_transposed(X, g):
     return (X.conj() * g[None, :]) @ X.T
 
@@ -312,6 +337,9 @@ MUTANTS = [
     ("Lanczos three-term dropped", dict(lanczos_run=_lanczos_missing_term),
      [pins.check_lanczos_full_spectrum]),
     ("gradient transposed", dict(eigval_grad=_grad_transposed), [pins.check_eigval_grad]),
+    ("degree rounded down", dict(degree_opt=_degree_floor), [pins.check_degree_opt]),
+    ("degree without margin", dict(degree_opt=_degree_no_margin), [pins.check_degree_opt]),
+    ("locking past nev", dict(lock_order=_lock_past_nev), [pins.check_lock_order]),
 ]
 
 
