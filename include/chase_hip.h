@@ -247,6 +247,17 @@ int chase_lanczos(const void* A, int64_t lda, int64_t N, const void* starts, int
 double chase_cond_est(const double* lam, double c, double e, const int32_t* degs, int32_t ne,
                       int32_t locked);
 
+/* Per-vector filter degrees of Alg. 2's degree optimisation (host
+ * computation, the solve's own routine): for each of the n pairs, the
+ * number of Chebyshev steps that takes resd[j] below tol_abs at the growth
+ * rate rho((lam[j] - c) / e), plus `extra`, clamped to [2, max_deg] and
+ * rounded up to even; max_deg inside the damped interval or for a
+ * non-finite residual.  resd, lam, degs (host) n entries each.  Returns -1
+ * for a null array, -3 for n < 0, -5 for e <= 0 or tol_abs <= 0, -7 for an
+ * odd or too small max_deg or a negative extra. */
+int chase_degree_opt(const double* resd, const double* lam, int32_t n, double c, double e, double tol_abs,
+                     int32_t max_deg, int32_t extra, int32_t* degs);
+
 /* ---- per-iteration trace (Sec. 4.2 and 4.3: CondEst against the computed
  * condition number of the filtered vectors, QR variant and phase times per
  * outer iteration) ----------------------------------------------------------- */

@@ -89,6 +89,7 @@ SIGNATURES = {
     "chase_rayleigh_ritz": (C.c_int, [_P, _I64, _P, _I64, _I64, _I64, _DP, _DP, _P]),
     "chase_lanczos": (C.c_int, [_P, _I64, _I64, _P, _I64, _I32, _I32, _I32, _DP, _P]),
     "chase_cond_est": (C.c_double, [_DP, _D, _D, _I32P, _I32, _I32]),
+    "chase_degree_opt": (C.c_int, [_DP, _DP, _I32, _D, _D, _D, _I32, _I32, _I32P]),
     "chase_create_real": (C.c_int, [_I64, C.POINTER(chase_params_t), C.POINTER(_P)]),
     "chase_solve_real": (C.c_int, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _I32, _DP, _DP,
                                    C.POINTER(chase_stats_t), _P]),
@@ -282,6 +283,15 @@ def chase_lanczos(A_ptr, lda, N, starts_ptr, ld_starts, nstarts, ksteps, ne, str
     check(load().chase_lanczos(A_ptr, lda, N, starts_ptr, ld_starts, nstarts, ksteps, ne, out,
                                stream), "chase_lanczos")
     return tuple(out)
+
+
+def chase_degree_opt(resd, lam, c, e, tol_abs, max_deg, extra):
+    n = len(resd)
+    rs = (C.c_double * n)(*[float(x) for x in resd])
+    la = (C.c_double * n)(*[float(x) for x in lam])
+    out = (C.c_int32 * n)()
+    check(load().chase_degree_opt(rs, la, n, c, e, tol_abs, max_deg, extra, out), "chase_degree_opt")
+    return [int(x) for x in out]
 
 
 def chase_cond_est(lam, c, e, degs, locked) -> float:

@@ -2096,6 +2096,16 @@ double chase_cond_est(const double* lam, double c, double e, const int32_t* degs
   return cond_est(lam, c, e, degs, ne, locked);
 }
 
+int chase_degree_opt(const double* resd, const double* lam, int32_t n, double c, double e, double tol_abs,
+                     int32_t max_deg, int32_t extra, int32_t* degs) {
+  if (n < 0) return -3;
+  if (n > 0 && (!resd || !lam || !degs)) return -1;
+  if (!(e > 0) || !(tol_abs > 0)) return -5;
+  if (max_deg < 2 || max_deg % 2 || extra < 0) return -7;
+  for (int32_t j = 0; j < n; ++j) degs[j] = degree_opt(resd[j], lam[j], c, e, tol_abs, max_deg, extra);
+  return kOk;
+}
+
 const char* chase_status_string(int status) {
   switch (status) {
     case 0: return "ok";

@@ -123,6 +123,34 @@ def test_workspace_bytes_memory_model():
     assert lib.chase_workspace_bytes(1000, ctypes.byref(bf), 2, ctypes.byref(out)) == -2
 
 
+def test_degree_opt_matches_oracle():
+    """The library's degree optimisation (the solve's own host routine)
+    against the oracle's, integer for integer, over random residuals and
+    Ritz values inside and outside the damped interval, including converged,
+    non-finite and capped cases."""
+    import oracle.core as oc
+    L = _lib()
+    rng = np.random.default_rng(2309)
+    for trial in range(200):
+        n = int(rng.integers(1, 40))
+        c, e = float(rng.normal()), float(rng.uniform(0.1, 3.0))
+        lam = c + e * rng.uniform(-4.0, 1.2, n)
+        resd = 10.0 ** rng.uniform(-13, 1, n)
+        resd[rng.random(n) < 0.05] = np.inf
+        tol = 10.0 ** float(rng.uniform(-12, -6))
+        max_deg = int(rng.choice([20, 36, 64]))
+        extra = int(rng.integers(0, 4))
+        got = L.chase_degree_opt(resd, lam, c, e, tol, max_deg, extra)
+        ref = oc.degree_opt(resd, lam, c, e, tol, max_deg, extra)
+        assert got == [int(x) for x in ref], (trial, got, list(ref))
+    lib = L.load()
+    out = (ctypes.c_int32 * 1)()
+    one = (ctypes.c_double * 1)(1.0)
+    assert lib.chase_degree_opt(None, one, 1, 0.0, 1.0, 1e-10, 36, 2, out) == -1
+    assert lib.chase_degree_opt(one, one, 1, 0.0, 0.0, 1e-10, 36, 2, out) == -5
+    assert lib.chase_degree_opt(one, one, 1, 0.0, 1.0, 1e-10, 35, 2, out) == -7
+
+
 def test_invalid_arguments_rejected_on_host():
     """Argument checks run before any device call."""
     L = _lib()
