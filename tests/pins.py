@@ -113,6 +113,36 @@ def check_lanczos_full_spectrum(oc, seed=8):
     assert abs(np.sum(np.abs(Z[0]) ** 2) - 1.0) <= 1e-12
 
 
+def dos_problem(N, seed):
+    """Hermitian A = Q diag(lam) Q^H and a Lanczos start whose squared
+    weights on the eigenvectors are 1.5/N, 1/N, ..., 1/N, 0.5/N (ascending
+    eigenvalues): N times the cumulative weight is j + 1.5 after the j-th
+    eigenvalue, so it first reaches any integer n_e at eigenvalue n_e, half a
+    step clear of rounding."""
+    rng = np.random.default_rng(seed)
+    lam = np.sort(rng.uniform(-2.0, 3.0, N))
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    A = (Q * lam) @ Q.conj().T
+    A = 0.5 * (A + A.conj().T)
+    w = np.full(N, 1.0 / N)
+    w[0], w[-1] = 1.5 / N, 0.5 / N
+    return lam, A, (Q @ np.sqrt(w))[:, None]
+
+
+def check_dos_closed_form(oc):
+    """The spectral-density estimate of mu_ne: with k = N Lanczos steps the
+    Ritz values are the eigenvalues and the quadrature weights the start's
+    squared components, so for the start of dos_problem mu_ne is exactly
+    the n_e-th eigenvalue; mu_1 the smallest, b_sup the largest."""
+    for seed in range(3):
+        for N in (10, 12):
+            lam, A, start = dos_problem(N, seed)
+            for ne in range(1, N - 1):
+                b_sup, mu_1, mu_ne, _ = oc.lanczos_bounds(A, start, ne, N)
+                assert abs(mu_ne - lam[ne - 1]) <= 1e-9, (seed, N, ne, mu_ne, lam[ne - 1])
+                assert abs(mu_1 - lam[0]) <= 1e-9 and abs(b_sup - lam[-1]) <= 1e-6
+
+
 # ----------------------------------------------------------------- CondEst
 
 def check_condest_golden(oc):

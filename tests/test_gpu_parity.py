@@ -191,6 +191,21 @@ def test_lanczos_matches_oracle(L, parity_problem):
     assert got[0] >= p.lam[-1] - 1e-12
 
 
+def test_lanczos_dos_closed_form(L):
+    """The library's Lanczos and spectral-density estimate on the closed-form
+    case of the oracle's pin: k = N steps from a start with designed weights
+    give mu_ne = the n_e-th eigenvalue exactly."""
+    from tests.pins import dos_problem
+    for seed in range(3):
+        for N in (10, 12):
+            lam, A, start = dos_problem(N, seed)
+            Ad, Sd = cm(A), cm(start)
+            for ne in range(1, N - 1):
+                b_sup, mu_1, mu_ne, _ = L.chase_lanczos(L.dptr(Ad), N, N, L.dptr(Sd), N, 1, N, ne, sp())
+                assert abs(mu_ne - lam[ne - 1]) <= 1e-9, (seed, N, ne, mu_ne, lam[ne - 1])
+                assert abs(mu_1 - lam[0]) <= 1e-9 and abs(b_sup - lam[-1]) <= 1e-6
+
+
 # ---------------------------------------------------------------- whole solve
 
 def solve_gpu(p, **kw):

@@ -16,6 +16,7 @@ PINS = [
     pins.check_filter_unit_at_mu1,
     pins.check_lanczos_bounds,
     pins.check_lanczos_full_spectrum,
+    pins.check_dos_closed_form,
     pins.check_condest_golden,
     pins.check_condest_overflow,
     pins.check_degree_opt,
@@ -313,6 +314,32 @@ def _lock_past_nev(resd_active, n_lockable, tol_abs):
     return oc.lock_order(resd_active, resd_active.shape[0], tol_abs)
 
 
+def _dos_next_count(A, starts, ne, k=25):
+    return oc.lanczos_bounds(A, starts, ne + 1, k)
+
+
+def _dos_last_component(A, starts, ne, k=25):
+    N = A.shape[0]
+    k = min(k, N)
+    R = starts.shape[1]
+    b_sup, mu_1, theta_max = -np.inf, np.inf, -np.inf
+    nodes, weights = [], []
+    for r in range(R):
+        alpha, beta = oc.lanczos_run(A, starts[:, r], k)
+        theta, Z = oc.tridiagonal_eig(alpha, beta)
+        b_sup = max(b_sup, theta[-1] + beta[-1])
+        mu_1 = min(mu_1, theta[0])
+        theta_max = max(theta_max, theta[-1])
+        nodes.append(theta)
+        weights.append(np.abs(Z[-1, :]) ** 2)
+    nodes, weights = np.concatenate(nodes), np.concatenate(weights)
+    order = np.argsort(nodes, kind="stable")
+    count = N * np.cumsum(weights[order]) / R
+    idx = min(int(np.searchsorted(count, ne, side="left")), nodes.shape[0] - 1)
+    mu_ne = min(max(float(nodes[order][idx]), mu_1), np.nextafter(b_sup, -np.inf))
+    return float(b_sup), float(mu_1), mu_ne, float(max(abs(mu_1), abs(theta_max)))
+
+
 def _grad_transposed(X, g):
     return (X.conj() * g[None, :]) @ X.T
 
@@ -340,6 +367,9 @@ MUTANTS = [
     ("degree rounded down", dict(degree_opt=_degree_floor), [pins.check_degree_opt]),
     ("degree without margin", dict(degree_opt=_degree_no_margin), [pins.check_degree_opt]),
     ("locking past nev", dict(lock_order=_lock_past_nev), [pins.check_lock_order]),
+    ("DoS count off by one", dict(lanczos_bounds=_dos_next_count), [pins.check_dos_closed_form]),
+    ("DoS weights from the last component", dict(lanczos_bounds=_dos_last_component),
+     [pins.check_dos_closed_form]),
 ]
 
 
