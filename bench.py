@@ -196,8 +196,7 @@ def main():
         torch.cuda.empty_cache()
         out["mixed"] = {}
         for name, code in (("fp32", L.CHASE_FP32_MIXED), ("bf16x3", L.CHASE_BF16X3_MIXED)):
-            with Solver(N, nev, nex, deg=20, max_deg=36, opt=1, tol=1e-10, precision=code,
-                        mixed_switch=1e-6, bf16_switch=1e-5) as ms:
+            with Solver(N, nev, nex, deg=20, max_deg=36, opt=1, tol=1e-10, precision=code) as ms:
                 mruns = []
                 for i in range(1 + 1):   # one warm-up, one timed
                     V.copy_(V0)

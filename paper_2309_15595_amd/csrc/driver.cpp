@@ -1397,8 +1397,8 @@ int chase_default_params(chase_params_t* p) {
   p->force_qr = CHASE_QR_AUTO;
   p->bounds_given = 0;
   p->tol = 1e-10;
-  p->mixed_switch = 1e-6;
-  p->bf16_switch = 1e-5;
+  p->mixed_switch = 5e-6;
+  p->bf16_switch = 2e-5;
   p->seed = 2309;
   return 0;
 }
