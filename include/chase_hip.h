@@ -121,7 +121,8 @@ int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h);
  *   variant  0: chase_create (complex128), 1: chase_create_real (float64;
  *            an odd N includes the zero-padded copy of H that every solve
  *            of an odd order uses; an odd lda at even N adds the same
- *            (N+1)^2 doubles on first use), 2: chase_create_c64
+ *            (N+1)^2 doubles on first use, and its first Householder QR
+ *            two N x n_e and one N x 32 complex128 blocks), 2: chase_create_c64
  *   bytes    (host) out
  * Not counted: the rocBLAS handle's own device-memory pool, which rocSOLVER's
  * eigensolver and QR calls grow on demand (of order n_e^2 words).

@@ -365,6 +365,19 @@ struct Workspace {
     if (st) release();
     return st;
   }
+  // Householder QR of a real block through the complex kernels (first use):
+  // the widened block, its Q and one panel of reflectors, 2N rows each
+  z64* hhXc = nullptr;
+  z64* hhQc = nullptr;
+  z64* hhVc = nullptr;
+  int ensure_hh_real() {
+    if (hhXc) return kOk;
+    const size_t M = (size_t)(2 * N);
+    int st = alloc(&hhXc, M * ne);
+    st = st ? st : alloc(&hhQc, M * ne);
+    st = st ? st : alloc(&hhVc, M * kHouseholderPanel);
+    return st;
+  }
   int ensure_hpad() {
     return Hpad ? kOk : alloc(&Hpad, (size_t)(2 * N) * (size_t)(2 * N));
   }
@@ -670,31 +683,30 @@ static int cholqr_pass(Workspace& w, z64* X, int64_t ldx, int64_t n, bool shifte
 }
 
 static int householder(Workspace& w, z64* X, int64_t ldx, int64_t n, hipStream_t s) {
-  if (!w.real) {
-    HouseholderWs h;
-    h.V = w.hhV;
-    h.T = w.hhT;
-    h.W1 = w.hhW;
-    h.W2 = w.hhW + (int64_t)kHouseholderPanel * w.ne;
-    h.part = w.hhpart;
-    h.rowj = w.hhrow;
-    h.tau = w.tau;
-    h.Q = w.B;
-    h.splitk = w.ws;
-    return householder_qr(X, ldx, w.N, n, h, s);
-  }
-  // the real block (a zero padding row stays zero): LAPACK's real routines
-  rocblas_set_stream(w.rb, s);
+  HouseholderWs h;
+  h.V = w.hhV;
+  h.T = w.hhT;
+  h.W1 = w.hhW;
+  h.W2 = w.hhW + (int64_t)kHouseholderPanel * w.ne;
+  h.part = w.hhpart;
+  h.rowj = w.hhrow;
+  h.tau = w.tau;
+  h.Q = w.B;
+  h.splitk = w.ws;
+  if (!w.real) return householder_qr(X, ldx, w.N, n, h, s);
+  // The real block (2N rows; a zero padding row stays zero) through the same
+  // kernels, widened with zero imaginary parts: every norm, reflector, tau and
+  // product of real operands then has an exactly zero imaginary part, so Q is
+  // the real Householder Q in LAPACK's conventions.
+  int st = w.ensure_hh_real();
+  if (st) return st;
+  const int64_t M = 2 * w.N;
   double* Xr = reinterpret_cast<double*>(X);
-  double* tau = reinterpret_cast<double*>(w.tau);
-  rocblas_status r = rocsolver_dgeqrf(w.rb, (rocblas_int)(2 * w.N), (rocblas_int)n, Xr, (rocblas_int)(2 * ldx), tau);
-  if (r == rocblas_status_success)
-    r = rocsolver_dorgqr(w.rb, (rocblas_int)(2 * w.N), (rocblas_int)n, (rocblas_int)n, Xr, (rocblas_int)(2 * ldx), tau);
-  if (r != rocblas_status_success) {
-    set_msg("rocsolver_dgeqrf/dorgqr failed");
-    return kHipError;
-  }
-  return kOk;
+  if ((st = widen_real_block(Xr, 2 * ldx, w.hhXc, M, M, n, s))) return st;
+  h.V = w.hhVc;
+  h.Q = w.hhQc;
+  if ((st = householder_qr(w.hhXc, M, M, n, h, s))) return st;
+  return real_part_block(w.hhXc, M, Xr, 2 * ldx, M, n, s);
 }
 
 // Alg. 4 with escalation on Cholesky failure.

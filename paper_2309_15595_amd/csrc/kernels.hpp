@@ -222,6 +222,10 @@ int dcopy_pad(const double* src, int64_t lds, int64_t rows_src, int64_t cols_src
 // R = Re(G) and G = R + 0 i for n x n blocks.
 int z_real_part(const z64* G, int64_t ldg, double* R, int64_t ldr, int64_t n, hipStream_t s);
 int d_to_z(const double* R, int64_t ldr, z64* G, int64_t ldg, int64_t n, hipStream_t s);
+// A real M x n block (leading dimension ldr, in doubles) as a complex128
+// block with zero imaginary parts, and back (the real parts).
+int widen_real_block(const double* R, int64_t ldr, z64* X, int64_t ldx, int64_t M, int64_t n, hipStream_t s);
+int real_part_block(const z64* X, int64_t ldx, double* R, int64_t ldr, int64_t M, int64_t n, hipStream_t s);
 // complex128 <-> complex64 conversions (column blocks); the widening one
 // multiplies by `scale` in FP64 (1 leaves the values as they are).
 int convert_z_to_c(const z64* src, int64_t lds, c32* dst, int64_t ldd, int64_t N, int64_t n,

@@ -252,6 +252,21 @@ __global__ void c2z_kernel(const c32* src, int64_t lds, zv* dst, int64_t ldd, in
   dst[m + j * ldd] = zv{(double)v.re * scale, (double)v.im * scale};
 }
 
+// real M x n block <-> complex128 block with zero imaginary parts
+__global__ void widen_real_kernel(const double* R, int64_t ldr, zv* X, int64_t ldx, int64_t M) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (m >= M) return;
+  X[m + j * ldx] = zv{R[m + j * ldr], 0.0};
+}
+
+__global__ void real_part_block_kernel(const zv* X, int64_t ldx, double* R, int64_t ldr, int64_t M) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (m >= M) return;
+  R[m + j * ldr] = X[m + j * ldx].re;
+}
+
 // ---- Lanczos ----------------------------------------------------------------
 
 // W[m, c] = sum_k A[m, k] V[k, c] = sum_k conj(A[k, m]) V[k, c]  (A Hermitian):
@@ -629,6 +644,22 @@ int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N
   if (n <= 0 || N <= 0) return kOk;
   hipLaunchKernelGGL(c2z_kernel, dim3((unsigned)cdiv(N, 256), (unsigned)n), dim3(256), 0, s, src, lds,
                      reinterpret_cast<zv*>(dst), ldd, N, scale);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int widen_real_block(const double* R, int64_t ldr, z64* X, int64_t ldx, int64_t M, int64_t n, hipStream_t s) {
+  if (n <= 0 || M <= 0) return kOk;
+  hipLaunchKernelGGL(widen_real_kernel, dim3((unsigned)cdiv(M, 256), (unsigned)n), dim3(256), 0, s, R, ldr,
+                     reinterpret_cast<zv*>(X), ldx, M);
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
+
+int real_part_block(const z64* X, int64_t ldx, double* R, int64_t ldr, int64_t M, int64_t n, hipStream_t s) {
+  if (n <= 0 || M <= 0) return kOk;
+  hipLaunchKernelGGL(real_part_block_kernel, dim3((unsigned)cdiv(M, 256), (unsigned)n), dim3(256), 0, s,
+                     reinterpret_cast<const zv*>(X), ldx, R, ldr, M);
   CHASE_CHK_LAUNCH();
   return kOk;
 }

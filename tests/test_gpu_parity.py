@@ -147,6 +147,24 @@ def test_householder_qr_matches_lapack(L, m, n):
     assert np.linalg.norm(Q.conj().T @ Q - np.eye(n), 2) <= 1e-13
 
 
+@pytest.mark.parametrize("m,n", [(1000, 300), (333, 37), (64, 64)])
+def test_householder_qr_real_block_matches_lapack(L, m, n):
+    """The real variant's Householder QR runs these kernels on the real block
+    widened with zero imaginary parts: Q is LAPACK's real Q (dgeqrf/dorgqr
+    through numpy) element by element, with imaginary parts exactly zero."""
+    rng = np.random.default_rng(m + 3 * n)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    W, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    X = (U * np.logspace(0, -4, n)) @ W.T
+    Xd = cm(X.astype(np.complex128))
+    v = L.chase_caqr(L.dptr(Xd), m, m, n, 1.0, oc.QR_HOUSEHOLDER, sp())
+    assert v == oc.QR_HOUSEHOLDER
+    Q = un(Xd)
+    assert np.all(Q.imag == 0.0)
+    ref = oc.householder_qr(X)
+    assert np.max(np.abs(Q.real - ref)) <= 1e-14 * 1e4 * max(n, 10), np.max(np.abs(Q.real - ref))
+
+
 def test_caqr_fallback_rank_deficient(L):
     X = pins.matrix_with_cond(300, 20, 10.0, seed=7)
     X[:, 5] = 0.0
