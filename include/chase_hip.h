@@ -145,6 +145,11 @@ int chase_solve(chase_handle_t h, const void* A, int64_t lda, void* V, int64_t l
                 const void* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
                 chase_stats_t* stats, chase_stream_t stream);  /* -1: null, real or complex64 handle */
 
+/* Frees every device buffer chase_create (or chase_create_real /
+ * chase_create_c64) allocated, and the handle itself; h must not be used
+ * afterwards.  The caller's buffers (H, V, starts) are never owned by the
+ * handle and stay untouched.  The caller must not destroy a handle while a
+ * solve on it is running.  Returns -1 for a null handle. */
 int chase_destroy(chase_handle_t h);
 
 /* Many independent problems of uneven N, each with its own params (FP64),
@@ -233,6 +238,35 @@ int chase_filter(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int6
 int chase_caqr(void* V, int64_t ldv, int64_t N, int64_t n, double cond, int32_t force,
                int32_t* variant, chase_stream_t stream);
 
+/* chase_caqr for a real block (float64, N x n, n <= N): the real solve's own
+ * route, the block read as complex row pairs (an odd order gets one zero
+ * row), Gram and quotient products keeping the real part, and the
+ * Householder branch on the block widened to complex128 with zero imaginary
+ * parts (LAPACK's real Q).  Allocates its workspace per call (2 on
+ * failure).  -1 null/unaligned V, -2 ldv < N, -3 N < 2, -4 n outside
+ * [1, N], -6 bad force. */
+int chase_caqr_real(double* V, int64_t ldv, int64_t N, int64_t n, double cond, int32_t force,
+                    int32_t* variant, chase_stream_t stream);
+
+/* The low-precision filter of the mixed solve (a column on the FP32 or the
+ * BF16x3 rung), as one call: the result approximates chase_filter's
+ * p_{d_j}(H) v_j (Eq. 1 with the same scaled coefficients) with FP32
+ * accumulation.
+ *   precision  CHASE_FP32_MIXED: complex64 copies of H and of the block,
+ *              FP32 matrix products; CHASE_BF16X3_MIXED: the four bfloat16
+ *              planes of H and of each iterate, three bfloat16 products per
+ *              real product (hi hi + hi lo + lo hi), FP32 accumulation
+ *   A (device) N x N complex128, read only; V (device) N x n complex128,
+ *   in/out (widened back to complex128 as each column reaches its degree);
+ *   degs (host) n even degrees >= 2, ascending; *matvecs (host) sum_j d_j.
+ * The copies of H (8 N^2 bytes for FP32, four bfloat16 planes for BF16x3)
+ * and the complex64 blocks are allocated per call (2 on failure).
+ * -1 null/unaligned A, -2 lda < N, -3 null/unaligned V, -4 ldv < N,
+ * -5 N < 2, -6 n outside [1, N], -7 bad degrees, -9 e <= 0, -11 precision. */
+int chase_filter_lowp(const void* A, int64_t lda, void* V, int64_t ldv, int64_t N, int64_t n,
+                      const int32_t* degs, double c, double e, double mu_1, int32_t precision,
+                      int64_t* matvecs, chase_stream_t stream);
+
 /* Rayleigh-Ritz (Alg. 2): Q (N x n, orthonormal) -> Ritz values theta
  * (host, n, ascending) and Ritz vectors written over Q; resid (host, n)
  * receives ||H x_j - theta_j x_j||. */
@@ -289,6 +323,26 @@ int chase_set_trace(chase_handle_t h, int32_t level);
 /* Copies up to cap records of the last traced solve on h to out (host);
  * *count (host) receives the number copied. */
 int chase_get_trace(chase_handle_t h, chase_trace_t* out, int32_t cap, int32_t* count);
+
+/* The active columns of one traced iteration, in the order they were
+ * filtered (trace level >= 1). */
+typedef struct {
+  int32_t origin;  /* the pair's rank in ascending Ritz value in the previous
+                      iteration's Rayleigh-Ritz output (its column index in
+                      the first iteration) */
+  int32_t rung;    /* precision of its filter: 0 FP64, 1 FP32, 2 BF16x3 */
+  int32_t degree;  /* its filter degree */
+  int32_t pad0;
+  double ritz;     /* its Ritz value from the previous iteration (0 in the first) */
+  double resid;    /* its FP64 residual norm from the previous iteration (inf in the first) */
+} chase_trace_column_t;
+
+/* Copies up to cap column records of iteration `iteration` (1-based) of the
+ * last traced solve on h to out (host); *count (host) receives the number
+ * copied.  -1 null handle, -2 no such traced iteration, -4 cap < 0 or a
+ * null out with cap > 0. */
+int chase_get_trace_columns(chase_handle_t h, int32_t iteration, chase_trace_column_t* out, int32_t cap,
+                            int32_t* count);
 
 const char* chase_status_string(int status);
 const char* chase_last_error(void);

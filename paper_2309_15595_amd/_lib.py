@@ -64,6 +64,16 @@ class chase_trace_t(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class chase_trace_column_t(C.Structure):
+    _fields_ = [
+        ("origin", C.c_int32), ("rung", C.c_int32), ("degree", C.c_int32), ("pad0", C.c_int32),
+        ("ritz", C.c_double), ("resid", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
+
+
 CHASE_TRACE_MAX = 256
 
 _I64, _I32, _D, _P = C.c_int64, C.c_int32, C.c_double, C.c_void_p
@@ -86,6 +96,9 @@ SIGNATURES = {
     "chase_filter": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D,
                                _I64P, _P]),
     "chase_caqr": (C.c_int, [_P, _I64, _I64, _I64, _D, _I32, _I32P, _P]),
+    "chase_caqr_real": (C.c_int, [_P, _I64, _I64, _I64, _D, _I32, _I32P, _P]),
+    "chase_filter_lowp": (C.c_int, [_P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D, _I32,
+                                    _I64P, _P]),
     "chase_rayleigh_ritz": (C.c_int, [_P, _I64, _P, _I64, _I64, _I64, _DP, _DP, _P]),
     "chase_lanczos": (C.c_int, [_P, _I64, _I64, _P, _I64, _I32, _I32, _I32, _DP, _P]),
     "chase_cond_est": (C.c_double, [_DP, _D, _D, _I32P, _I32, _I32]),
@@ -100,6 +113,7 @@ SIGNATURES = {
                                   C.POINTER(chase_stats_t), _P]),
     "chase_set_trace": (C.c_int, [_P, _I32]),
     "chase_get_trace": (C.c_int, [_P, C.POINTER(chase_trace_t), _I32, _I32P]),
+    "chase_get_trace_columns": (C.c_int, [_P, _I32, C.POINTER(chase_trace_column_t), _I32, _I32P]),
     "chase_status_string": (C.c_char_p, [C.c_int]),
     "chase_last_error": (C.c_char_p, []),
 }
@@ -268,6 +282,20 @@ def chase_caqr(V_ptr, ldv, N, n, cond, force, stream) -> int:
     v = C.c_int32(-1)
     check(load().chase_caqr(V_ptr, ldv, N, n, cond, force, C.byref(v), stream), "chase_caqr")
     return v.value
+
+
+def chase_caqr_real(V_ptr, ldv, N, n, cond, force, stream) -> int:
+    v = C.c_int32(-1)
+    check(load().chase_caqr_real(V_ptr, ldv, N, n, cond, force, C.byref(v), stream), "chase_caqr_real")
+    return v.value
+
+
+def chase_filter_lowp(A_ptr, lda, V_ptr, ldv, N, n, degs, c, e, mu_1, precision, stream) -> int:
+    d = (C.c_int32 * n)(*[int(x) for x in degs])
+    mv = C.c_int64(0)
+    check(load().chase_filter_lowp(A_ptr, lda, V_ptr, ldv, N, n, d, c, e, mu_1, precision,
+                                   C.byref(mv), stream), "chase_filter_lowp")
+    return mv.value
 
 
 def chase_rayleigh_ritz(A_ptr, lda, Q_ptr, ldq, N, n, stream):

@@ -88,6 +88,18 @@ class Solver:
                    "chase_get_trace")
         return [buf[i].as_dict() for i in range(n.value)]
 
+    def trace_columns(self, iteration: int):
+        """The active columns of a traced iteration (1-based), in filter order:
+        dicts of origin (ascending-Ritz-value rank in the previous iteration),
+        rung (0 FP64, 1 FP32, 2 BF16x3), degree, ritz and resid."""
+        import ctypes
+        cap = self.nev + self.nex
+        buf = (_lib.chase_trace_column_t * cap)()
+        n = ctypes.c_int32(0)
+        _lib.check(_lib.load().chase_get_trace_columns(self.h, int(iteration), buf, cap, ctypes.byref(n)),
+                   "chase_get_trace_columns")
+        return [buf[i].as_dict() for i in range(n.value)]
+
     def __enter__(self):
         return self
 

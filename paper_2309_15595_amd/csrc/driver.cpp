@@ -4,9 +4,10 @@
 //
 // Device work all runs in the hand-written kernels of zgemm.hip, zfilter.hip,
 // bfilter.hip, zgrad.hip, hhqr.hip and small.hip, except the n_e x n_e
-// eigensolve of Rayleigh-Ritz (rocSOLVER zheevd / dsyevd), the real type
-// variant's Householder QR (rocSOLVER dgeqrf / dorgqr) and the trace's
-// singular values (rocSOLVER zgesvd / dgesvd, studies only).
+// eigensolve of Rayleigh-Ritz (rocSOLVER zheevd / dsyevd) and the trace's
+// singular values (rocSOLVER zgesvd / dgesvd, studies only).  The real type
+// variant's Householder QR runs the complex hhqr.hip kernels on its block
+// widened to complex128 with zero imaginary parts.
 //
 // Three element types share the loop: complex128 (chase_solve), real
 // symmetric float64 (chase_solve_real: real columns read as complex row
@@ -55,13 +56,23 @@ static double rho_of(double t) {
   return std::max(std::abs(t - s), std::abs(t + s));
 }
 
-// Alg. 5.
+// Alg. 5.  The estimate reads the first column and the first active column
+// of the block sorted by degree (ties in ascending Ritz value): the active
+// column of smallest degree, and among those the smallest Ritz value, which
+// is also the first column when nothing is locked.  Taking that column by
+// search gives the same value for any order of the active columns, so the
+// mixed-precision solve, whose block is sorted by rung first, gets the
+// estimate of its degree-sorted view.
 static double cond_est(const double* Lam, double c, double e, const int32_t* degs, int ne, int locked) {
-  const double t_first = (Lam[0] - c) / e;
-  const double t_active = (Lam[locked] - c) / e;
-  const int d = degs[locked];
-  int d_max = d;
-  for (int j = locked; j < ne; ++j) d_max = std::max(d_max, (int)degs[j]);
+  int js = locked;
+  int d_max = degs[locked];
+  for (int j = locked + 1; j < ne; ++j) {
+    if (degs[j] < degs[js] || (degs[j] == degs[js] && Lam[j] < Lam[js])) js = j;
+    d_max = std::max(d_max, (int)degs[j]);
+  }
+  const double t_first = ((locked > 0 ? Lam[0] : Lam[js]) - c) / e;
+  const double t_active = (Lam[js] - c) / e;
+  const int d = degs[js];
   return std::pow(rho_of(t_active), d) * std::pow(rho_of(t_first), d_max - d);
 }
 
@@ -371,12 +382,21 @@ struct Workspace {
   z64* hhQc = nullptr;
   z64* hhVc = nullptr;
   int ensure_hh_real() {
-    if (hhXc) return kOk;
+    if (hhXc && hhQc && hhVc) return kOk;
     const size_t M = (size_t)(2 * N);
-    int st = alloc(&hhXc, M * ne);
-    st = st ? st : alloc(&hhQc, M * ne);
-    st = st ? st : alloc(&hhVc, M * kHouseholderPanel);
+    int st = hhXc ? kOk : alloc(&hhXc, M * ne);
+    st = st ? st : (hhQc ? kOk : alloc(&hhQc, M * ne));
+    st = st ? st : (hhVc ? kOk : alloc(&hhVc, M * kHouseholderPanel));
+    if (st) {  // free what this call allocated: the next use retries from scratch
+      for (z64** p : {&hhXc, &hhQc, &hhVc}) free_one(reinterpret_cast<void**>(p));
+    }
     return st;
+  }
+  void free_one(void** p) {
+    if (!*p) return;
+    if (!counting) (void)hipFree(*p);
+    owned.erase(std::remove(owned.begin(), owned.end(), *p), owned.end());
+    *p = nullptr;
   }
   int ensure_hpad() {
     return Hpad ? kOk : alloc(&Hpad, (size_t)(2 * N) * (size_t)(2 * N));
@@ -627,6 +647,48 @@ static int run_filter_lowp(int64_t N, z64* V, int64_t ldv, c32* X0, c32* X1, int
   if (matvecs) *matvecs = mv;
   if (launches) *launches = nl;
   return kOk;
+}
+
+// The BF16x3 rung: columns V[:, 0:n) (degrees ascending) through the
+// split-product step on the bfloat16 planes of conj(H) in w.P16, with the
+// complex64 ping-pong blocks w.X32a / w.X32b and their planes w.XP16a /
+// w.XP16b (each step's epilogue writes the planes of the block it produces).
+static int filter_rung_bf16(Workspace& w, z64* V, int64_t ldv, int64_t n, const int32_t* degs, double c, double e,
+                            double mu1, double lam_lo, int64_t* mv, int64_t* nl, hipStream_t s) {
+  const int64_t N = w.N, ldp = w.ldp, xps = w.ldp * w.ne;
+  uint16_t* const XP[2] = {w.XP16a, w.XP16b};
+  bool first = true;
+  auto launch = [&](const CGemmArgs& a, bool cur0, int64_t s0) {
+    int r;
+    if (first) {  // planes of the starting block (step 0 reads X0 from column 0)
+      first = false;
+      if ((r = bsplit_block(a.B, a.ldb, a.K, a.N, XP[0], ldp, xps, s))) return r;
+    }
+    BGemmArgs b;
+    b.M = a.M; b.N = a.N; b.K = a.K;
+    b.P = w.P16; b.ldp = ldp; b.plane_stride = ldp * N;
+    b.X = a.B; b.ldx = a.ldb;
+    b.Y = a.Y; b.ldy = a.ldy;
+    b.Z = a.Z; b.ldz = a.ldz;
+    b.alpha = a.alpha; b.beta = a.beta; b.gamma = a.gamma;
+    b.Xp = XP[cur0 ? 0 : 1] + s0 * ldp; b.ldxp = ldp; b.xps = xps;
+    b.Yp = XP[cur0 ? 1 : 0] + s0 * ldp; b.ldyp = ldp; b.yps = xps;
+    return bfilter_launch(b, s, w.tail_ws, w.tail_counters);
+  };
+  return run_filter_lowp(N, V, ldv, w.X32a, w.X32b, n, degs, c, e, mu1, lam_lo, mv, nl, s, launch);
+}
+
+// The FP32 rung: the same on complex64 H (H32, leading dimension ld32).
+static int filter_rung_fp32(Workspace& w, const c32* H32, int64_t ld32, z64* V, int64_t ldv, int64_t n,
+                            const int32_t* degs, double c, double e, double mu1, double lam_lo, int64_t* mv,
+                            int64_t* nl, hipStream_t s) {
+  auto launch = [&](const CGemmArgs& a, bool, int64_t) {
+    CGemmArgs b = a;
+    b.A = H32;
+    b.lda = ld32;
+    return cfilter_big_launch(b, s, w.tail_ws, w.tail_counters);
+  };
+  return run_filter_lowp(w.N, V, ldv, w.X32a, w.X32b, n, degs, c, e, mu1, lam_lo, mv, nl, s, launch);
 }
 
 // Gram matrix G = X^H X (Hermitised), X: N x n.
@@ -997,6 +1059,11 @@ struct ProblemState {
   std::vector<int32_t> degs;
   std::vector<double> Lam, resd, prev_resd, th_h, rs_h;
   std::vector<char> low;  // precision rung of each column: 2 BF16x3, 1 FP32, 0 FP64
+  // Rayleigh-Ritz returns the active pairs in ascending Ritz value.  origin[j]
+  // is that rank for the pair in column j (its column index before the first
+  // iteration); it moves with the column through every permutation.
+  std::vector<int> origin;
+  std::vector<int> sort_order;  // the permutation prepare() applied this iteration (empty: none)
   int locked = 0, it = 1;
   double bnd[4] = {0, 0, 0, 0};
   double b_sup = 0, mu_ne = 0, c = 0, e = 1, mu1_cur = 0, tol_abs = 0, sw_abs = 0, sw16_abs = 0;
@@ -1006,6 +1073,8 @@ struct ProblemState {
   PhaseTimer t_lz, t_f, t_qr, t_rr;
   int trace_level = 0;
   std::vector<chase_trace_t>* trace = nullptr;
+  std::vector<chase_trace_column_t>* trace_cols = nullptr;  // per traced iteration, its active columns
+  std::vector<int64_t>* trace_col_off = nullptr;            // start of each iteration's columns
   chase_trace_t rec{};  // the iteration being traced
   const c32* A32 = nullptr;  // H for the FP32 rung: the library's copy, or a complex64 caller's own
   int64_t lda32 = 0;
@@ -1030,12 +1099,26 @@ struct ProblemState {
     std::vector<T> tmp(arr.begin() + locked, arr.end());
     for (int j = 0; j < na(); ++j) arr[locked + j] = tmp[order[j]];
   }
+  template <class T>
+  void unpermute_active(std::vector<T>& arr, const std::vector<int>& order) {
+    std::vector<T> tmp(arr.begin() + locked, arr.end());
+    for (int j = 0; j < na(); ++j) arr[locked + order[j]] = tmp[j];
+  }
   void permute_state(const std::vector<int>& order) {
     permute_active(Lam, order);
     permute_active(resd, order);
     permute_active(degs, order);
     permute_active(low, order);
     permute_active(prev_resd, order);
+    permute_active(origin, order);
+  }
+  void unpermute_state(const std::vector<int>& order) {
+    unpermute_active(Lam, order);
+    unpermute_active(resd, order);
+    unpermute_active(degs, order);
+    unpermute_active(low, order);
+    unpermute_active(prev_resd, order);
+    unpermute_active(origin, order);
   }
 
   // Initial block, Lanczos bounds (Alg. 2 first line), FP32 copy of H.
@@ -1090,6 +1173,16 @@ struct ProblemState {
     resd.assign(ne, std::numeric_limits<double>::infinity());
     prev_resd = resd;
     low.assign(ne, w->c64 ? (char)1 : (char)P.precision);  // complex64: every column on the FP32 rung
+    // With nex = 0 the largest Ritz value is a wanted one, and from the second
+    // iteration on it is the lower end of the damped interval [mu_ne, b_sup]:
+    // the filter then no longer separates that pair from the eigenvalues above
+    // it, so the rounding a low rung leaves in it could never be filtered out.
+    // Its column (the largest Ritz value after the first Rayleigh-Ritz) runs in
+    // FP64 from the start.
+    if (mixed && !w->c64 && P.nex == 0) low[ne - 1] = 0;
+    origin.resize(ne);
+    std::iota(origin.begin(), origin.end(), 0);
+    sort_order.clear();
     th_h.assign(ne, 0.0);
     rs_h.assign(ne, 0.0);
     return copy_columns(V, ldv, w->C2, N, N, ne, s);
@@ -1113,10 +1206,12 @@ struct ProblemState {
     });
     bool ident = true;
     for (int j = 0; j < na(); ++j) ident = ident && order[j] == j;
+    sort_order.clear();
     if (ident) return kOk;
     int st = apply_perm(*w, V + (int64_t)locked * ldv, ldv, order, false, 0, s);
     if (st) return st;
     permute_state(order);
+    sort_order = order;
     return kOk;
   }
 
@@ -1161,33 +1256,8 @@ struct ProblemState {
     const int n16 = mixed ? n_rung(2) : 0, n32 = mixed ? n_rung(1) : 0;
     if (n16 > 0) {
       int64_t mv16 = 0, nl16 = 0;
-      const uint16_t* P16 = w->P16;
-      const int64_t ldp = w->ldp;
-      void* tw = w->tail_ws;
-      int* tc = w->tail_counters;
-      // the bfloat16 planes of the two complex64 buffers, column for column
-      uint16_t* const XP[2] = {w->XP16a, w->XP16b};
-      const int64_t xps = ldp * ne;
-      bool first = true;
-      auto launch = [&](const CGemmArgs& a, bool cur0, int64_t s0) {
-        int r;
-        if (first) {  // planes of the starting block (step 0 reads X0 from column 0)
-          first = false;
-          if ((r = bsplit_block(a.B, a.ldb, a.K, a.N, XP[0], ldp, xps, s))) return r;
-        }
-        BGemmArgs b;
-        b.M = a.M; b.N = a.N; b.K = a.K;
-        b.P = P16; b.ldp = ldp; b.plane_stride = ldp * N;
-        b.X = a.B; b.ldx = a.ldb;
-        b.Y = a.Y; b.ldy = a.ldy;
-        b.Z = a.Z; b.ldz = a.ldz;
-        b.alpha = a.alpha; b.beta = a.beta; b.gamma = a.gamma;
-        b.Xp = XP[cur0 ? 0 : 1] + s0 * ldp; b.ldxp = ldp; b.xps = xps;
-        b.Yp = XP[cur0 ? 1 : 0] + s0 * ldp; b.ldyp = ldp; b.yps = xps;
-        return bfilter_launch(b, s, tw, tc);
-      };
-      if ((st = run_filter_lowp(N, V + (int64_t)locked * ldv, ldv, w->X32a, w->X32b, n16, degs.data() + locked,
-                                c, e, mu1_cur, lam_lo(), &mv16, &nl16, s, launch)))
+      if ((st = filter_rung_bf16(*w, V + (int64_t)locked * ldv, ldv, n16, degs.data() + locked, c, e, mu1_cur,
+                                 lam_lo(), &mv16, &nl16, s)))
         return st;
       S.filter_matvecs_bf16 += mv16;
       mv += mv16;
@@ -1195,18 +1265,8 @@ struct ProblemState {
     }
     if (n32 > 0) {
       int64_t mv32 = 0, nl32 = 0;
-      const c32* H32 = A32;
-      const int64_t ld32 = lda32;
-      void* tw = w->tail_ws;
-      int* tc = w->tail_counters;
-      auto launch = [&](const CGemmArgs& a, bool, int64_t) {
-        CGemmArgs b = a;
-        b.A = H32;
-        b.lda = ld32;
-        return cfilter_big_launch(b, s, tw, tc);
-      };
-      if ((st = run_filter_lowp(N, V + (int64_t)(locked + n16) * ldv, ldv, w->X32a, w->X32b, n32,
-                                degs.data() + locked + n16, c, e, mu1_cur, lam_lo(), &mv32, &nl32, s, launch)))
+      if ((st = filter_rung_fp32(*w, A32, lda32, V + (int64_t)(locked + n16) * ldv, ldv, n32,
+                                 degs.data() + locked + n16, c, e, mu1_cur, lam_lo(), &mv32, &nl32, s)))
         return st;
       S.filter_matvecs_fp32 += mv32;
       mv += mv32;
@@ -1258,6 +1318,18 @@ struct ProblemState {
       for (int j = locked; j < ne; ++j) rec.filter_matvecs += degs[j];
       rec.kappa_est = cond;
       rec.kappa_com = rec.kappa_com_active = rec.kappa_com_equil = std::nan("");
+      if (trace_cols && trace_col_off && trace->size() < CHASE_TRACE_MAX) {
+        trace_col_off->push_back((int64_t)trace_cols->size());
+        for (int j = locked; j < ne; ++j) {
+          chase_trace_column_t col{};
+          col.origin = origin[j];
+          col.rung = mixed ? low[j] : 0;
+          col.degree = degs[j];
+          col.ritz = Lam[j];
+          col.resid = resd[j];
+          trace_cols->push_back(col);
+        }
+      }
       if (trace_level > 1) {
         if ((st = kappa_of_block(*w, V, ldv, ne, false, s, &rec.kappa_com))) return st;
         if ((st = kappa_of_block(*w, V + (int64_t)locked * ldv, ldv, na(), false, s, &rec.kappa_com_active)))
@@ -1295,18 +1367,30 @@ struct ProblemState {
       rec.t_rr = t_rr.acc - acc0[2];
       trace->push_back(rec);
     }
+    // Rayleigh-Ritz returned the pairs in ascending Ritz value, the order the
+    // active columns had before prepare() sorted them: undo that sort on the
+    // per-pair state, so that each pair keeps its own rung and residual.
+    if (!sort_order.empty()) {
+      unpermute_state(sort_order);
+      sort_order.clear();
+    }
     for (int j = 0; j < na(); ++j) {
       Lam[locked + j] = th_h[j];
       prev_resd[locked + j] = resd[locked + j];
       resd[locked + j] = rs_h[j];
+      origin[locked + j] = j;
       if (!std::isfinite(th_h[j]) || !std::isfinite(rs_h[j])) breakdown = true;
     }
     if (breakdown) return kOk;
-    if (mixed && !w->c64)  // a column moves down a rung at the rung's floor or once it stops improving
+    if (mixed && !w->c64)
       for (int j = locked; j < ne; ++j) {
-        const bool stalled = resd[j] > 0.5 * prev_resd[j];
-        if (low[j] == 2 && (resd[j] <= sw16_abs || stalled)) low[j] = 1;
-        else if (low[j] == 1 && (resd[j] <= sw_abs || stalled)) low[j] = 0;
+        // one rung down once the pair stops improving (residual above half
+        // the previous one); below a rung's floor it leaves that rung at once
+        int r = low[j];
+        if (r > 0 && resd[j] > 0.5 * prev_resd[j]) --r;
+        if (r == 2 && resd[j] <= sw16_abs) r = 1;
+        if (r == 1 && resd[j] <= sw_abs) r = 0;
+        low[j] = (char)r;
       }
 
     // Deflation and locking
@@ -1390,6 +1474,8 @@ struct chase_handle_s {
   bool c64 = false;   // created by chase_create_c64
   int trace_level = 0;
   std::vector<chase_trace_t> trace;  // of the last solve
+  std::vector<chase_trace_column_t> trace_cols;  // its active columns, iteration after iteration
+  std::vector<int64_t> trace_col_off;            // where each iteration's columns start
 };
 
 extern "C" {
@@ -1475,7 +1561,11 @@ int chase_solve(chase_handle_t h, const void* A_, int64_t lda, void* V_, int64_t
   ps.P = h->p;
   ps.trace_level = h->trace_level;
   ps.trace = &h->trace;
+  ps.trace_cols = &h->trace_cols;
+  ps.trace_col_off = &h->trace_col_off;
   h->trace.clear();
+  h->trace_cols.clear();
+  h->trace_col_off.clear();
   ps.A = reinterpret_cast<const z64*>(A_);
   ps.lda = lda;
   ps.V = reinterpret_cast<z64*>(V_);
@@ -1566,7 +1656,11 @@ int chase_solve_real(chase_handle_t h, const double* A, int64_t lda, double* V, 
   ps.P = h->p;
   ps.trace_level = h->trace_level;
   ps.trace = &h->trace;
+  ps.trace_cols = &h->trace_cols;
+  ps.trace_col_off = &h->trace_col_off;
   h->trace.clear();
+  h->trace_cols.clear();
+  h->trace_col_off.clear();
   ps.A = Apair;
   ps.lda = ldpair;
   ps.V = w.Cint;
@@ -1643,7 +1737,11 @@ int chase_solve_c64(chase_handle_t h, const void* A, int64_t lda, void* V, int64
   ps.P = h->p;
   ps.trace_level = h->trace_level;
   ps.trace = &h->trace;
+  ps.trace_cols = &h->trace_cols;
+  ps.trace_col_off = &h->trace_col_off;
   h->trace.clear();
+  h->trace_cols.clear();
+  h->trace_col_off.clear();
   ps.A = nullptr;  // every product with H goes through the FP32 kernels
   ps.lda = 0;
   ps.V = w.Cint;
@@ -1733,6 +1831,20 @@ int chase_get_trace(chase_handle_t h, chase_trace_t* out, int32_t cap, int32_t* 
   if (cap < 0 || (cap > 0 && !out)) return -3;
   const int32_t n = std::min<int32_t>(cap, (int32_t)h->trace.size());
   for (int32_t i = 0; i < n; ++i) out[i] = h->trace[(size_t)i];
+  if (count) *count = n;
+  return kOk;
+}
+
+int chase_get_trace_columns(chase_handle_t h, int32_t iteration, chase_trace_column_t* out, int32_t cap,
+                            int32_t* count) {
+  if (!h) return -1;
+  if (iteration < 1 || iteration > (int32_t)h->trace_col_off.size()) return -2;
+  if (cap < 0 || (cap > 0 && !out)) return -4;
+  const size_t i = (size_t)iteration - 1;
+  const int64_t b = h->trace_col_off[i];
+  const int64_t e = i + 1 < h->trace_col_off.size() ? h->trace_col_off[i + 1] : (int64_t)h->trace_cols.size();
+  const int32_t n = (int32_t)std::min<int64_t>(cap, e - b);
+  for (int32_t j = 0; j < n; ++j) out[j] = h->trace_cols[(size_t)(b + j)];
   if (count) *count = n;
   return kOk;
 }
@@ -2049,6 +2161,80 @@ int chase_caqr(void* V, int64_t ldv, int64_t N, int64_t n, double cond, int32_t 
   }
   w.release();
   if (!st && variant) *variant = v;
+  return st;
+}
+
+int chase_caqr_real(double* V, int64_t ldv, int64_t N, int64_t n, double cond, int32_t force, int32_t* variant,
+                    chase_stream_t stream) {
+  if (!V || !aligned16(V)) return -1;
+  if (ldv < N) return -2;
+  if (N < 2) return -3;
+  if (n < 1 || n > N) return -4;
+  if (force < -1 || force > 3) return -6;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Workspace w;
+  int st = w.create_real(N, (int)n);
+  if (st) return st;
+  // the block in the row-pair layout of the real solve (an odd order gets a
+  // zero row), through the same 1D-CAQR, and back
+  const int64_t np = w.N;
+  double* Cr = reinterpret_cast<double*>(w.Cint);
+  int v = 0;
+  st = dcopy_pad(V, ldv, N, n, Cr, 2 * np, 2 * np, n, s);
+  if (!st) st = caqr(w, w.Cint, np, n, cond, force, &v, s);
+  if (!st) st = dcopy_pad(Cr, 2 * np, N, n, V, ldv, N, n, s);
+  if (!st) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      set_last_error("chase_caqr_real", e);
+      st = kHipError;
+    }
+  }
+  w.release();
+  if (!st && variant) *variant = v;
+  return st;
+}
+
+int chase_filter_lowp(const void* A, int64_t lda, void* V, int64_t ldv, int64_t N, int64_t n, const int32_t* degs,
+                      double c, double e, double mu_1, int32_t precision, int64_t* matvecs, chase_stream_t stream) {
+  if (!A || !aligned16(A)) return -1;
+  if (lda < N) return -2;
+  if (!V || !aligned16(V)) return -3;
+  if (ldv < N) return -4;
+  if (N < 2) return -5;
+  if (n < 1 || n > N) return -6;
+  if (!degs) return -7;
+  for (int64_t j = 0; j < n; ++j)
+    if (degs[j] < 2 || degs[j] % 2 || (j > 0 && degs[j] < degs[j - 1])) return -7;
+  if (!(e > 0)) return -9;
+  if (precision != CHASE_FP32_MIXED && precision != CHASE_BF16X3_MIXED) return -11;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool bf16 = precision == CHASE_BF16X3_MIXED;
+  Workspace w;
+  int st = w.create(N, (int)n, true, false, bf16);
+  if (st) return st;
+  const z64* H = reinterpret_cast<const z64*>(A);
+  z64* X = reinterpret_cast<z64*>(V);
+  // the range guard's lower estimate of the spectrum, as in the solve: mu_1
+  // less 1 % of its distance to the upper bound c + e
+  const double lam_lo = mu_1 - 0.01 * std::fabs(c + e - mu_1);
+  int64_t mv = 0, nl = 0;
+  if (bf16) {
+    st = bsplit_planes(H, lda, N, w.P16, s);
+    if (!st) st = filter_rung_bf16(w, X, ldv, n, degs, c, e, mu_1, lam_lo, &mv, &nl, s);
+  } else {
+    st = convert_z_to_c(H, lda, w.A32, N, N, N, s);
+    if (!st) st = filter_rung_fp32(w, w.A32, N, X, ldv, n, degs, c, e, mu_1, lam_lo, &mv, &nl, s);
+  }
+  if (!st) {
+    hipError_t err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+      set_last_error("chase_filter_lowp", err);
+      st = kHipError;
+    }
+  }
+  w.release();
+  if (!st && matvecs) *matvecs = mv;
   return st;
 }
 

@@ -78,6 +78,39 @@ def test_cond_est_matches_oracle_golden():
     assert L.chase_cond_est([-1.0, 0.0, 0.5], 1.0, 1e-3, [200, 200, 200], 0) == np.inf
 
 
+def test_cond_est_any_order_of_active_columns():
+    """The mixed-precision solve sorts its active block by rung, then degree.
+    Alg. 5 reads the block sorted by degree (ties in ascending Ritz value, the
+    order Rayleigh-Ritz leaves): the library's estimate of a rung-sorted
+    block equals the oracle's on the degree-sorted one."""
+    import oracle.core as oc
+    L = _lib()
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        ne = int(rng.integers(2, 30))
+        locked = int(rng.integers(0, ne))
+        c, e = 2.0, float(rng.uniform(0.5, 3.0))
+        lam = np.sort(rng.uniform(-2.0, 4.0, ne))     # Rayleigh-Ritz order
+        degs = rng.choice(np.arange(2, 38, 2), ne)
+        # the oracle's block: active columns stable-sorted by degree
+        order = np.argsort(degs[locked:], kind="stable")
+        lam_d, degs_d = lam.copy(), degs.copy()
+        lam_d[locked:] = lam[locked:][order]
+        degs_d[locked:] = degs[locked:][order]
+        ref = oc.cond_est(lam_d, c, e, degs_d, locked)
+        # a two-rung block: a random subset of the active columns first
+        rung = rng.integers(0, 2, ne - locked)
+        order2 = sorted(range(ne - locked), key=lambda j: (-rung[j], degs[locked + j], j))
+        lam_r, degs_r = lam.copy(), degs.copy()
+        lam_r[locked:] = lam[locked:][order2]
+        degs_r[locked:] = degs[locked:][order2]
+        got = L.chase_cond_est(lam_r.tolist(), c, e, degs_r.tolist(), locked)
+        if np.isinf(ref):
+            assert np.isinf(got)
+        else:
+            assert abs(got - ref) <= 1e-12 * ref, (trial, got, ref)
+
+
 def test_workspace_bytes_memory_model():
     """Eq. (2) at p = q = 1 on the host, with no device call.  Eq. (2) counts
     N^2 + 4 N n_e + n_e^2 words; the caller holds H and V (N^2 + N n_e), the
@@ -170,6 +203,9 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.chase_set_trace(None, 1) == -1
     assert lib.chase_get_trace(None, None, 0, None) == -1
     assert lib.chase_filter(None, 10, None, 10, None, 10, 10, 1, None, 0.0, 1.0, -1.0, None, None) == -1
+    assert lib.chase_caqr_real(None, 10, 10, 2, 1.0, -1, None, None) == -1
+    assert lib.chase_filter_lowp(None, 10, None, 10, 10, 1, None, 0.0, 1.0, -1.0, 1, None, None) == -1
+    assert lib.chase_get_trace_columns(None, 1, None, 0, None) == -1
     assert np.isnan(L.chase_cond_est([1.0], 0.0, 0.0, [2], 0))
 
 
@@ -184,14 +220,15 @@ def test_struct_sizes_match_c_compiler(tmp_path):
         pytest.skip("no host C compiler")
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "chase_hip.h"\n'
-                   'int main(void){printf("%zu %zu %zu\\n", sizeof(chase_params_t), sizeof(chase_stats_t),'
-                   ' sizeof(chase_trace_t));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(chase_params_t), sizeof(chase_stats_t),'
+                   ' sizeof(chase_trace_t), sizeof(chase_trace_column_t));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     assert int(out[0]) == ctypes.sizeof(L.chase_params_t)
     assert int(out[1]) == ctypes.sizeof(L.chase_stats_t)
     assert int(out[2]) == ctypes.sizeof(L.chase_trace_t)
+    assert int(out[3]) == ctypes.sizeof(L.chase_trace_column_t)
 
 
 def _build_c_example(out_path):

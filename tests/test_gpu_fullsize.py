@@ -3,8 +3,6 @@ times.  The oracle cannot solve these; they are checked against properties
 that hold at any size (the prescribed spectrum, residual and orthogonality
 bounds), against single-problem solves, and on sampled outputs the CPU
 computes one by one."""
-import os
-
 import numpy as np
 import pytest
 
@@ -188,13 +186,19 @@ def test_eigval_grad_50000_sampled(L):
         assert abs(Gs[a] - ref) <= bound, (i, j, abs(Gs[a] - ref), bound)
 
 
-@pytest.mark.skipif(os.environ.get("CHASE_FULL_50000") != "1",
-                    reason="N = 50000 (40 GB H, minutes of GPU time): set CHASE_FULL_50000=1 to run")
+def _progress(msg):
+    """A line per finished step of a long test, past pytest's capture."""
+    import sys
+    print(f"[test_differentiable_50000] {msg}", file=sys.__stderr__, flush=True)
+
+
+@pytest.mark.timeout(900)
 def test_differentiable_50000(L):
     """The differentiable workload end to end: N = 50000 DFT-like H, nev 2000,
     nex 400, loss sum_i w_i lambda_i; eigenvalues against the prescribed
-    spectrum, the backward G = X diag(w) X^H checked on sampled entries
-    against the formula evaluated on the host from the returned X."""
+    spectrum and against sampled host residuals of the returned vectors, the
+    backward G = X diag(w) X^H of the solve's own eigenvectors checked on
+    sampled entries against the formula evaluated on the host."""
     import time
     N, nev, nex = 50000, 2000, 400
     lam = synth.dft_like_spectrum(N)
@@ -204,12 +208,21 @@ def test_differentiable_50000(L):
         synth.complex_gaussian(np.random.default_rng(sp.SEED_V0), (N, nev + nex)).T)).cuda()
     S = torch.from_numpy(np.ascontiguousarray(
         synth.complex_gaussian(np.random.default_rng(sp.SEED_LANCZOS), (N, 4)).T)).cuda()
+    torch.cuda.synchronize()
+    _progress("H (40 GB), initial block and Lanczos starts resident; solving")
     t0 = time.perf_counter()
     ritz, resid, info, V = _solve(L, A, V0, S, nev, nex)
     t_solve = time.perf_counter() - t0
+    _progress(f"solve done in {t_solve:.1f} s, status {info.status}")
     assert info.converged, info.stats
     assert np.max(np.abs(ritz - lam[:nev])) <= 1e-10 * normA
     assert np.max(resid) <= 1e-10 * normA
+    # sampled residuals of the returned vectors (the solved matrix is conj(A))
+    for j in (0, nev // 2, nev - 1):
+        x = V[j]
+        r = torch.conj(A @ torch.conj(x)) - ritz[j] * x
+        assert float(torch.linalg.vector_norm(r)) <= 1e-10 * normA * (1 + 1e-6)
+    assert _ortho(V, nev) <= 1e-12
     w = torch.from_numpy(sp.loss_weights(nev)).cuda()
     del A
     torch.cuda.empty_cache()
@@ -219,6 +232,7 @@ def test_differentiable_50000(L):
     L.chase_eigval_grad(N, nev, L.dptr(V), N, L.dptr(w), L.dptr(G), N, 0, L.stream_ptr())
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t1
+    _progress(f"backward done in {t_grad * 1e3:.0f} ms; checking sampled entries")
     Xh = V[:nev].cpu().numpy()
     wh = w.cpu().numpy()
     rng = np.random.default_rng(7)

@@ -49,10 +49,17 @@ def sp():
 
 # ---------------------------------------------------------------- filter
 
+# N = 1100, 300 columns: eight full 128-row panels and a ragged one, two full
+# 128-column tiles (the full-tile instantiation the N = 20000 solve runs) and
+# a ragged third, the split-K tail of the last round, every even degree
+DEGS_1100 = sorted(np.random.default_rng(1100).choice(np.arange(2, 38, 2), 300).tolist())
+
+
 @pytest.mark.parametrize("N,degs", [
     (517, [2, 2, 4, 6, 6, 10, 20, 20, 36] + [20] * 60 + [36] * 7),   # ragged N, 76 columns
     (800, [20] * 80),
     (130, [2, 4]),
+    (1100, DEGS_1100),
 ])
 def test_filter_matches_oracle(L, N, degs):
     rng = np.random.default_rng(N)
@@ -112,6 +119,37 @@ def test_filter_leading_dimension(L):
     assert np.max(np.abs(got[:N] - ref)) <= 1e-11 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_filter_lowp_matches_oracle(L, prec):
+    """The FP32 and BF16x3 filter steps of the mixed solve against the FP64
+    oracle, column by column, at N = 1100 with 300 columns of every even
+    degree.  Each step's products carry a relative error of at most u per
+    product (FP32: u = 2^-24 from the complex64 operands and FP32
+    accumulation; BF16x3: u = 2^-16 from the 16-bit hi + lo split of both
+    operands and the dropped lo*lo term); the scaled recurrence keeps every
+    iterate within the start's norm and passes each step's error on through
+    the same bounded recurrence, so after d steps the column error stays
+    below 4 d u ||v|| (the normwise error of a step is u ||alpha (H - c)|| ||x||,
+    with ||alpha (H - c)|| <= 2 here)."""
+    N = 1100
+    u = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[prec]
+    code = {"fp32": L.CHASE_FP32_MIXED, "bf16x3": L.CHASE_BF16X3_MIXED}[prec]
+    rng = np.random.default_rng(N)
+    lam = np.sort(rng.uniform(-1.0, 2.0, N))
+    A = synth.hermitian_from_spectrum(lam, "gaussian", seed=N)
+    degs = np.array(DEGS_1100)
+    V = synth.complex_gaussian(rng, (N, degs.size))
+    c, e, mu1 = 1.1, 0.9, lam[0] + 1e-3
+    ref, mv_ref = oc.chebyshev_filter(A, V, degs, c, e, mu1)
+    Ad, Vd = cm(A), cm(V)
+    mv = L.chase_filter_lowp(L.dptr(Ad), N, L.dptr(Vd), N, N, degs.size, degs, c, e, mu1, code, sp())
+    got = un(Vd)
+    assert mv == mv_ref
+    ratio = np.linalg.norm(got - ref, axis=0) / (degs * u * np.linalg.norm(V, axis=0))
+    print(f"\n{prec}: max |x - x_ref| / (d u |v|) = {ratio.max():.3f}, median {np.median(ratio):.4f}")
+    assert ratio.max() <= 4.0, ratio.max()
+
+
 # ---------------------------------------------------------------- CAQR
 
 @pytest.mark.parametrize("kappa,force", [(5.0, 0), (1e5, 1), (1e7, 1), (1e12, 2), (1e14, 2),
@@ -165,6 +203,29 @@ def test_householder_qr_real_block_matches_lapack(L, m, n):
     assert np.max(np.abs(Q.real - ref)) <= 1e-14 * 1e4 * max(n, 10), np.max(np.abs(Q.real - ref))
 
 
+@pytest.mark.parametrize("m", [301, 400])
+@pytest.mark.parametrize("force", [0, 1, 2, 3, -1])
+def test_caqr_real_matches_oracle(L, m, force):
+    """The real variant's 1D-CAQR on its own route (the real block read as
+    complex row pairs, an odd order padded with one zero row, Householder on
+    the block widened to complex128): Q equals the oracle's real Q element
+    by element (CholeskyQR's Q is unique; the Householder branch is LAPACK's),
+    at an odd and an even order."""
+    n = 37
+    kappa = {0: 5.0, 1: 1e6, 2: 1e12, 3: 1e3, -1: 1e3}[force]
+    rng = np.random.default_rng(m + 7 * force)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    W, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    X = (U * np.logspace(0, -np.log10(kappa), n)) @ W.T
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    v = L.chase_caqr_real(L.dptr(Xd), m, m, n, kappa, force, sp())
+    Q = Xd.cpu().numpy().T
+    ref, vref = oc.caqr(X.astype(np.complex128), kappa, None if force < 0 else force)
+    assert v == vref
+    assert np.linalg.norm(Q.T @ Q - np.eye(n), 2) <= 1e-13
+    assert np.max(np.abs(Q - ref.real)) <= max(1e-12, 1e-14 * kappa * n), np.max(np.abs(Q - ref.real))
+
+
 def test_caqr_fallback_rank_deficient(L):
     X = pins.matrix_with_cond(300, 20, 10.0, seed=7)
     X[:, 5] = 0.0
@@ -177,7 +238,7 @@ def test_caqr_fallback_rank_deficient(L):
 
 # ---------------------------------------------------------------- Rayleigh-Ritz
 
-@pytest.mark.parametrize("N,n", [(800, 80), (333, 37)])
+@pytest.mark.parametrize("N,n", [(800, 80), (333, 37), (1100, 300)])
 def test_rayleigh_ritz_matches_oracle(L, N, n):
     rng = np.random.default_rng(N + n)
     lam = np.linspace(-1, 1, N)
@@ -277,27 +338,83 @@ def test_solve_tiny_orders(L, N, nev, nex, prec):
     At N = 2 the first Ritz value lands far above the smallest eigenvalue, so
     the next filter, normalised there, grows that eigenvector's component by
     about 1e43: past the FP32 range, which the low-precision rungs must
-    absorb without a breakdown.  With nex = 0 the damped interval reaches
-    down to the wanted Ritz value, so once that value is accurate the filter
-    no longer separates the two eigenvalues: the FP64 oracle gets there in
-    one step from a poor Ritz value, while a low rung stops at FP32 accuracy
-    and the FP64 rung then stalls.  Those cases check the range guard only
-    (no breakdown, the FP32-accurate eigenvalue)."""
+    absorb without a breakdown.  With nex = 0 the largest Ritz value is a
+    wanted one and the damped interval's lower end, so its column runs in FP64
+    from the start on every rung; every rung must reach the oracle's outcome
+    and eigenvalues."""
     p = synth.make_problem(N, nev, nex, spectrum="uniform", basis="gaussian", seed=300 + N)
     code = {"fp64": L.CHASE_FP64, "fp32": L.CHASE_FP32_MIXED, "bf16x3": L.CHASE_BF16X3_MIXED}[prec]
-    if prec != "fp64" and nex == 0:
-        from paper_2309_15595_amd.api import Solver
-        with Solver(p.N, p.nev, p.nex, precision=code, max_iter=4) as s:
-            ritz, resid, info = s.solve_colmajor(cm(p.A), cm(p.V0), True, cm(p.starts))
-        assert info.status in (0, 1), info.stats
-        assert info.stats["filter_matvecs_fp32"] + info.stats["filter_matvecs_bf16"] > 0
-        assert np.max(np.abs(ritz - p.lam[:nev])) <= 1e-6 * p.norm2
-        return
     ritz, resid, X, info = solve_gpu(p, precision=code)
     r = oc.chase(p.A, oc.Params(nev=nev, nex=nex), V0=p.V0, starts=p.starts)
     assert info.converged == r.converged, info.stats
     assert np.max(np.abs(ritz - r.evals)) <= 1e-10 * p.norm2
     assert np.max(np.abs(ritz - p.lam[:nev])) <= 1e-10 * p.norm2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_ladder_rungs_follow_their_pairs(L, parity_problem, parity_oracle, prec):
+    """The rung of each column, as the filter ran it (per-iteration column
+    trace), against the pair it holds: pairs are followed from one iteration
+    to the next by their rank in ascending Ritz value (Rayleigh-Ritz returns
+    the pairs in that order).  A pair never climbs back to a lower-precision
+    rung, and a column runs on rung r > 0 only while its last FP64 residual
+    is above that rung's floor (FP32 5e-6, BF16x3 2e-5, times ||H||_est)."""
+    from paper_2309_15595_amd.api import Solver
+    p = parity_problem
+    code = {"fp32": L.CHASE_FP32_MIXED, "bf16x3": L.CHASE_BF16X3_MIXED}[prec]
+    with Solver(p.N, p.nev, p.nex, precision=code) as s:
+        s.set_trace(1)
+        ritz, resid, info = s.solve_colmajor(cm(p.A), cm(p.V0), True, cm(p.starts))
+        tr = s.trace()
+        cols = [s.trace_columns(t["iteration"]) for t in tr]
+    assert info.converged
+    assert np.max(np.abs(ritz - parity_oracle.evals)) <= 1e-10 * p.norm2
+    norm = info.stats["bounds"][3]
+    floor = {1: 5e-6 * norm, 2: 2e-5 * norm}
+    top = {"fp32": 1, "bf16x3": 2}[prec]
+    assert all(c["rung"] == top for c in cols[0])          # every column starts on the top rung
+    rungs_seen = set()
+    for t in range(len(tr)):
+        cc = cols[t]
+        assert len(cc) == tr[t]["n_active"]
+        assert sum(c["degree"] for c in cc) == tr[t]["filter_matvecs"]
+        for c in cc:
+            rungs_seen.add(c["rung"])
+            if t > 0 and c["rung"] > 0:
+                assert c["resid"] > floor[c["rung"]], (t, c)
+        if t == 0:
+            continue
+        prev = sorted(cols[t - 1], key=lambda c: c["origin"])   # position = rank the RR gave
+        assert sorted(c["origin"] for c in cc) == sorted(set(c["origin"] for c in cc))
+        for c in cc:
+            assert c["rung"] <= prev[c["origin"]]["rung"], (t, c, prev[c["origin"]])
+    assert 0 in rungs_seen and top in rungs_seen
+    print(f"\n{prec}: {info.stats['iterations']} iterations, rungs per iteration "
+          + str([[sum(c['rung'] == r for c in cc) for r in (2, 1, 0)] for cc in cols]))
+
+
+def test_trace_columns_fp64(L):
+    """The column trace of an FP64 solve: rung 0 everywhere, origins the
+    ranks of the previous Rayleigh-Ritz, Ritz values ascending within each
+    degree (the stable sort by degree of a block in ascending Ritz value)."""
+    from paper_2309_15595_amd.api import Solver
+    p = synth.make_problem(300, 12, 6, seed=9)
+    with Solver(p.N, p.nev, p.nex) as s:
+        s.set_trace(1)
+        _, _, info = s.solve_colmajor(cm(p.A), cm(p.V0), True, cm(p.starts))
+        tr = s.trace()
+        cols = [s.trace_columns(t["iteration"]) for t in tr]
+        with pytest.raises(ValueError):
+            s.trace_columns(len(tr) + 1)
+    assert [c["origin"] for c in cols[0]] == list(range(p.ne))
+    for t, cc in enumerate(cols):
+        assert all(c["rung"] == 0 for c in cc)
+        degs = [c["degree"] for c in cc]
+        assert degs == sorted(degs)
+        if t > 0:
+            for a, b in zip(cc, cc[1:]):
+                if a["degree"] == b["degree"]:
+                    assert a["ritz"] <= b["ritz"] and a["origin"] < b["origin"]
 
 
 @pytest.mark.parametrize("force", [0, 1, 2, 3])
