@@ -231,6 +231,31 @@ int chase_filter(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int6
                  int64_t n, const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs,
                  chase_stream_t stream);
 
+/* Allocation-free chase_filter, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, layout and result as chase_filter;
+ * W stays the caller's ping-pong buffer.  The split-K tail's partial tiles
+ * and counters live in one fixed device array of the library (the scratch:
+ * CHASE_FILTER_NOALLOC_SEGMENTS partial 128 x 128 complex128 tiles plus 4160
+ * bytes of counters, 64 MiB + 4160 B, chase_filter_noalloc_scratch_bytes()),
+ * which every GPU the library runs on holds until the process ends; its
+ * address is looked up on the first call on each device.  No device memory
+ * is allocated or freed.  Every call on a GPU shares that GPU's scratch, and
+ * the counters are cleared by a fill kernel at the start of each call: calls
+ * that overlap on one GPU (different streams, threads or processes) race;
+ * calls on one stream are ordered.  The work is enqueued on stream and the
+ * call returns without waiting (*matvecs, host, is set at once).  The tail
+ * split of every step is planned within the scratch, so every N and n is
+ * accepted; a step whose split would not fit is rejected with -12 and a
+ * message in chase_last_error().  Other statuses as chase_filter
+ * (3: HIP error, e.g. the scratch's address could not be found). */
+#define CHASE_FILTER_NOALLOC_SEGMENTS 256
+int chase_filter_noalloc(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int64_t ldw, int64_t N,
+                         int64_t n, const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs,
+                         chase_stream_t stream);
+/* Bytes of the scratch array of chase_filter_noalloc. */
+int64_t chase_filter_noalloc_scratch_bytes(void);
+
 /* 1D-CAQR (Alg. 4): V (N x n) is replaced by an orthonormal basis of its
  * span with the variant chosen from cond (or forced, CHASE_QR_*).
  * *variant (host) receives the variant that succeeded (after escalation

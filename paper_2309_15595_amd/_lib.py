@@ -95,6 +95,9 @@ SIGNATURES = {
     "chase_eigval_grad": (C.c_int, [_I64, _I32, _P, _I64, _P, _P, _I64, _I32, _P]),
     "chase_filter": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D,
                                _I64P, _P]),
+    "chase_filter_noalloc": (C.c_int, [_P, _I64, _P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D,
+                                       _I64P, _P]),
+    "chase_filter_noalloc_scratch_bytes": (_I64, []),
     "chase_caqr": (C.c_int, [_P, _I64, _I64, _I64, _D, _I32, _I32P, _P]),
     "chase_caqr_real": (C.c_int, [_P, _I64, _I64, _I64, _D, _I32, _I32P, _P]),
     "chase_filter_lowp": (C.c_int, [_P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D, _I32,
@@ -275,6 +278,16 @@ def chase_filter(A_ptr, lda, V_ptr, ldv, W_ptr, ldw, N, n, degs, c, e, mu_1, str
     mv = C.c_int64(0)
     check(load().chase_filter(A_ptr, lda, V_ptr, ldv, W_ptr, ldw, N, n, d, c, e, mu_1,
                               C.byref(mv), stream), "chase_filter")
+    return mv.value
+
+
+def chase_filter_noalloc(A_ptr, lda, V_ptr, ldv, W_ptr, ldw, N, n, degs, c, e, mu_1, stream) -> int:
+    """chase_filter on the library's fixed device scratch: allocates nothing
+    and returns once the work is enqueued on `stream`."""
+    d = (C.c_int32 * max(1, n))(*[int(x) for x in degs])
+    mv = C.c_int64(0)
+    check(load().chase_filter_noalloc(A_ptr, lda, V_ptr, ldv, W_ptr, ldw, N, n, d, c, e, mu_1,
+                                      C.byref(mv), stream), "chase_filter_noalloc")
     return mv.value
 
 

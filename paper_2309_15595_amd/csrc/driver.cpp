@@ -536,13 +536,14 @@ static void as_real_steps(std::vector<GemmArgs>& steps) {
 
 static int run_filter(const z64* A, int64_t lda, z64* V, int64_t ldv, z64* W, int64_t ldw, int64_t N,
                       int64_t n, const int32_t* degs, double c, double e, double mu1, int64_t* matvecs,
-                      int64_t* launches, hipStream_t s, void* tail_ws, int* tail_counters, bool real = false) {
+                      int64_t* launches, hipStream_t s, void* tail_ws, int* tail_counters, bool real = false,
+                      int max_segments = kTailMaxSegments) {
   std::vector<GemmArgs> steps = plan_filter(A, lda, V, ldv, W, ldw, N, n, degs, c, e, mu1);
   if (real) as_real_steps(steps);
   int64_t mv = 0;
   for (const GemmArgs& g : steps) {
     int st = real ? dfilter_big_launch(g, s, tail_ws, tail_counters)
-                  : zgemm_nn_big_launch(g, s, true, tail_ws, tail_counters);
+                  : zgemm_nn_big_launch(g, s, true, tail_ws, tail_counters, kChoiceT0Tail, max_segments);
     if (st) return st;
     mv += g.N;
   }
@@ -1462,6 +1463,44 @@ static int check_solve_args(int64_t N, const void* A, int64_t lda, const void* V
   return kOk;
 }
 
+// Argument checks of chase_filter (and of its allocation-free variant).
+int filter_check_args(const void* A, int64_t lda, const void* V, int64_t ldv, const void* W, int64_t ldw, int64_t N,
+                      int64_t n, const int32_t* degs, double e) {
+  if (!A || !aligned16(A)) return -1;
+  if (lda < N) return -2;
+  if (!V || !aligned16(V)) return -3;
+  if (ldv < N) return -4;
+  if (!W || !aligned16(W)) return -5;
+  if (ldw < N) return -6;
+  if (N < 1) return -7;
+  if (n < 0) return -8;
+  if (n > 0 && !degs) return -9;
+  // even degrees >= 2, ascending: every column's last iterate lands in V
+  for (int64_t j = 0; j < n; ++j)
+    if (degs[j] < 2 || degs[j] % 2 || (j > 0 && degs[j] < degs[j - 1])) return -9;
+  if (!(e > 0)) return -11;
+  return kOk;
+}
+
+// The complex filter on caller-owned tail scratch (max_segments partial tiles
+// at tail_ws, kTailCounterInts counters), enqueued on s without waiting.  The
+// counters are cleared by a fill kernel first.
+int filter_on_scratch(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int64_t ldw, int64_t N, int64_t n,
+                      const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs, void* tail_ws,
+                      int* tail_counters, int max_segments, hipStream_t s) {
+  int st = tail_counters_init(tail_counters, s);
+  int64_t mv = 0, nl = 0;
+  if (!st)
+    st = run_filter(reinterpret_cast<const z64*>(A), lda, reinterpret_cast<z64*>(V), ldv,
+                    reinterpret_cast<z64*>(W), ldw, N, n, degs, c, e, mu_1, &mv, &nl, s, tail_ws, tail_counters,
+                    false, max_segments);
+  if (st < 0) {  // a launch refused a split larger than the scratch (the planner keeps to the cap)
+    set_msg("chase_filter_noalloc: a step's split-K tail needs more partial tiles than the scratch holds");
+    return -12;
+  }
+  if (!st && matvecs) *matvecs = mv;
+  return st;
+}
 
 }  // namespace chase
 
@@ -2100,19 +2139,7 @@ int chase_eigval_grad(int64_t N, int32_t nev, const void* X, int64_t ldx, const 
 
 int chase_filter(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int64_t ldw, int64_t N, int64_t n,
                  const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs, chase_stream_t stream) {
-  if (!A || !aligned16(A)) return -1;
-  if (lda < N) return -2;
-  if (!V || !aligned16(V)) return -3;
-  if (ldv < N) return -4;
-  if (!W || !aligned16(W)) return -5;
-  if (ldw < N) return -6;
-  if (N < 1) return -7;
-  if (n < 0) return -8;
-  if (n > 0 && !degs) return -9;
-  // even degrees >= 2, ascending: every column's last iterate lands in V
-  for (int64_t j = 0; j < n; ++j)
-    if (degs[j] < 2 || degs[j] % 2 || (j > 0 && degs[j] < degs[j - 1])) return -9;
-  if (!(e > 0)) return -11;
+  if (int bad = filter_check_args(A, lda, V, ldv, W, ldw, N, n, degs, e)) return bad;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   void* tws = nullptr;
   int* tcnt = nullptr;

@@ -56,8 +56,10 @@ struct TileGeom {
 // costs its busiest SIMD's share of MFMA work: an edge tile whose live
 // columns fit in the first half of the waves costs half a tile).
 // counters: kTailCounterInts ints.  Returns the grid.
+// max_segments (<= kTailMaxSegments) caps the partial tiles of the split, for
+// callers whose workspace holds fewer than kTailMaxSegments of them.
 int64_t plan_schedule(const TileGeom& geo, int64_t nkt, int64_t resident, int min_kt_per_seg, bool allow_split,
-                      void* ws, int* counters, TailSplit* t);
+                      void* ws, int* counters, TailSplit* t, int max_segments = kTailMaxSegments);
 int64_t tail_workspace_bytes();
 int tail_counters_init(int* counters, hipStream_t s);
 // Large NN products (filter step, H C): 128 x 128 tiles, double-buffered LDS
@@ -72,7 +74,7 @@ constexpr int kChoiceT0NoTail = 1;  // 128 x 128, no tail split
 constexpr int kChoiceT1Tail = 2;    // 128 x 64, split-K tail
 constexpr int kNumChoices = 3;
 int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws, int* tail_counters,
-                        int choice = kChoiceT0Tail);
+                        int choice = kChoiceT0Tail, int max_segments = kTailMaxSegments);
 // One problem's filter GEMM in a grouped launch: tiles [tile_end - tiles,
 // tile_end) of the step's running tile count belong to it.
 struct GroupEntry {
@@ -232,5 +234,15 @@ int convert_z_to_c(const z64* src, int64_t lds, c32* dst, int64_t ldd, int64_t N
                    hipStream_t s);
 int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N, int64_t n,
                    hipStream_t s, double scale = 1.0);
+
+// Argument checks of chase_filter (driver.cpp): 0, or the negative status.
+int filter_check_args(const void* A, int64_t lda, const void* V, int64_t ldv, const void* W, int64_t ldw, int64_t N,
+                      int64_t n, const int32_t* degs, double e);
+// chase_filter's steps on caller-owned tail scratch: max_segments partial
+// 128 x 128 complex128 tiles at tail_ws and kTailCounterInts ints at
+// tail_counters (cleared by a fill kernel first); enqueued on s, no wait.
+int filter_on_scratch(const void* A, int64_t lda, void* V, int64_t ldv, void* W, int64_t ldw, int64_t N, int64_t n,
+                      const int32_t* degs, double c, double e, double mu_1, int64_t* matvecs, void* tail_ws,
+                      int* tail_counters, int max_segments, hipStream_t s);
 
 }  // namespace chase

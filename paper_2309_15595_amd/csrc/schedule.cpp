@@ -87,7 +87,8 @@ int64_t grid_for(int64_t resident, int64_t full, int64_t nseg) {
 
 struct PlanCache {
   std::mutex mu;
-  std::map<std::tuple<int64_t, int64_t, int64_t, int, int, int, int, int64_t, int, bool>, std::pair<int64_t, int64_t>>
+  std::map<std::tuple<int64_t, int64_t, int64_t, int, int, int, int, int64_t, int, bool, int>,
+           std::pair<int64_t, int64_t>>
       plans;
 };
 PlanCache& plan_cache() {
@@ -98,7 +99,8 @@ PlanCache& plan_cache() {
 }  // namespace
 
 int64_t plan_schedule(const TileGeom& g, int64_t nkt, int64_t resident, int min_kt_per_seg, bool allow_split,
-                      void* ws, int* counters, TailSplit* t) {
+                      void* ws, int* counters, TailSplit* t, int max_segments) {
+  max_segments = std::max(0, std::min(max_segments, kTailMaxSegments));
   const int64_t tiles_n = cdiv(g.N, g.bn);
   const int64_t tiles = cdiv(g.M, g.bm) * tiles_n;
   t->full = tiles;
@@ -108,7 +110,7 @@ int64_t plan_schedule(const TileGeom& g, int64_t nkt, int64_t resident, int min_
   t->queue = counters + kTailMaxSegments;
   if (allow_split && ws && tiles > 0) {
     const auto key = std::make_tuple(g.M, g.N, nkt, g.bm, g.bn, g.wgm, g.wgn * 1000 + g.narrow_cols, resident,
-                                     min_kt_per_seg, allow_split);
+                                     min_kt_per_seg, allow_split, max_segments);
     PlanCache& pc = plan_cache();
     std::lock_guard<std::mutex> lock(pc.mu);
     auto it = pc.plans.find(key);
@@ -127,7 +129,7 @@ int64_t plan_schedule(const TileGeom& g, int64_t nkt, int64_t resident, int min_
       for (int64_t r : cands) {
         if (r <= 0 || r > tiles) continue;
         for (int64_t ks = 2; ks <= 8; ++ks) {
-          if (nkt < (int64_t)min_kt_per_seg * ks || r * ks > kTailMaxSegments) break;
+          if (nkt < (int64_t)min_kt_per_seg * ks || r * ks > max_segments) break;
           const int64_t full = tiles - r;
           const double m = simulate(g, tiles, full, ks, grid_for(resident, full, r * ks), cost);
           if (m < best - 1e-6) {

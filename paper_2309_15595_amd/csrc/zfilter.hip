@@ -938,7 +938,7 @@ int tail_counters_init(int* counters, hipStream_t s) {
 }
 
 int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, void* tail_ws, int* tail_counters,
-                        int choice) {
+                        int choice, int max_segments) {
   if (g.M <= 0 || g.N <= 0) return kOk;
   if (g.ws != nullptr || g.upper_b || g.lower_only || g.bscale != nullptr) return -1;
   if (!tail_ws || !tail_counters) return -1;
@@ -949,7 +949,9 @@ int zgemm_nn_big_launch(const GemmArgs& g, hipStream_t s, bool filter_symbol, vo
   if (cfg == 0) geo.narrow_cols = 32;  // the direct-to-LDS step's narrow edge layout
   TailSplit t;
   const int64_t grid = plan_schedule(geo, cdiv(g.K, c.bk), (int64_t)cu_count() * c.wg_per_cu, 16,
-                                     choice != kChoiceT0NoTail, tail_ws, tail_counters, &t);
+                                     choice != kChoiceT0NoTail, tail_ws, tail_counters, &t, max_segments);
+  if ((cdiv(g.M, c.bm) * cdiv(g.N, c.bn) - t.full) * t.ksplit > max_segments)
+    return -1;  // the planner keeps to the cap; a split past it would overrun tail_ws
   GemmArgs a = g;
   if (a.K <= 0) a.alpha = 0.0;
   if (!filter_symbol)
