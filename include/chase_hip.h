@@ -84,7 +84,7 @@ typedef struct {
   int32_t iterations;
   int32_t locked;
   int32_t qr_count[4];      /* CholQR1, CholQR2, shifted CholQR2, Householder */
-  int32_t pad0;
+  int32_t eig_sweeps;       /* block-Jacobi sweeps of the quotient eigensolves, summed */
   int64_t filter_matvecs;   /* sum over iterations of sum_j d_j */
   int64_t filter_matvecs_fp32; /* of which in FP32 (mixed precision) */
   int64_t filter_matvecs_bf16; /* of which in BF16x3 (mixed precision) */
@@ -298,6 +298,25 @@ int chase_filter_lowp(const void* A, int64_t lda, void* V, int64_t ldv, int64_t 
 int chase_rayleigh_ritz(const void* A, int64_t lda, void* Q, int64_t ldq, int64_t N, int64_t n,
                         double* theta, double* resid, chase_stream_t stream);
 
+/* The small eigensolve of Rayleigh-Ritz (Alg. 2: the n x n Hermitian
+ * quotient; Sec. 3.1's dense solver step), as chase_solve runs it: two-sided
+ * block Jacobi on the GPU (blocks of 16, pairs of blocks diagonalised in
+ * LDS by cyclic complex plane rotations, the 32 x 32 products applied to the
+ * whole matrix and to the eigenvector accumulator), until the largest
+ * off-diagonal entry of a sweep is below 1e-10 max|G_ii| (the sweep then
+ * ends at rounding level).
+ *   G (device) n x n, leading dimension ldg >= n, column-major complex128:
+ *   the lower triangle is read (the diagonal's imaginary parts are taken as
+ *   zero); on return G holds the orthonormal eigenvectors, column j for
+ *   theta[j].  A real symmetric G (zero imaginary parts) gets real
+ *   eigenvectors.  theta (host) n eigenvalues, ascending.  *sweeps (host,
+ *   nullable) the number of sweeps made.
+ * Workspace (2 (n rounded up to 32)^2 complex128 and less than 1 MiB more)
+ * is allocated per call (2 on failure).  Host-synchronous.
+ * -1 null/unaligned G, -2 ldg < n, -3 n outside [1, 65536], -4 null theta;
+ * 4 non-finite entries (or no convergence in 40 sweeps). */
+int chase_heev(void* G, int64_t ldg, int64_t n, double* theta, int32_t* sweeps, chase_stream_t stream);
+
 /* Lanczos bounds (reading of Alg. 1's first line): (b_sup, mu_1, mu_ne,
  * norm_est) into out[4] (host) from nstarts runs of ksteps. */
 int chase_lanczos(const void* A, int64_t lda, int64_t N, const void* starts, int64_t ld_starts,
@@ -335,6 +354,8 @@ typedef struct {
    * so this is the figure its accuracy depends on). */
   double kappa_com, kappa_com_active, kappa_com_equil;
   double t_filter, t_qr, t_rr;  /* seconds, HIP events on the solve's stream */
+  int32_t eig_sweeps;      /* block-Jacobi sweeps of this iteration's quotient eigensolve */
+  int32_t pad0;
 } chase_trace_t;
 
 /* Trace the next chase_solve calls on h: level 0 off (default), 1 records a

@@ -36,7 +36,7 @@ class chase_params_t(C.Structure):
 class chase_stats_t(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("iterations", C.c_int32), ("locked", C.c_int32),
-        ("qr_count", C.c_int32 * 4), ("pad0", C.c_int32),
+        ("qr_count", C.c_int32 * 4), ("eig_sweeps", C.c_int32),
         ("filter_matvecs", C.c_int64), ("filter_matvecs_fp32", C.c_int64),
         ("filter_matvecs_bf16", C.c_int64),
         ("total_matvecs", C.c_int64), ("filter_launches", C.c_int64),
@@ -58,10 +58,11 @@ class chase_trace_t(C.Structure):
         ("qr_variant", C.c_int32), ("filter_matvecs", C.c_int64), ("kappa_est", C.c_double),
         ("kappa_com", C.c_double), ("kappa_com_active", C.c_double), ("kappa_com_equil", C.c_double),
         ("t_filter", C.c_double), ("t_qr", C.c_double), ("t_rr", C.c_double),
+        ("eig_sweeps", C.c_int32), ("pad0", C.c_int32),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
 
 
 class chase_trace_column_t(C.Structure):
@@ -103,6 +104,7 @@ SIGNATURES = {
     "chase_filter_lowp": (C.c_int, [_P, _I64, _P, _I64, _I64, _I64, _I32P, _D, _D, _D, _I32,
                                     _I64P, _P]),
     "chase_rayleigh_ritz": (C.c_int, [_P, _I64, _P, _I64, _I64, _I64, _DP, _DP, _P]),
+    "chase_heev": (C.c_int, [_P, _I64, _I64, _DP, _I32P, _P]),
     "chase_lanczos": (C.c_int, [_P, _I64, _I64, _P, _I64, _I32, _I32, _I32, _DP, _P]),
     "chase_cond_est": (C.c_double, [_DP, _D, _D, _I32P, _I32, _I32]),
     "chase_degree_opt": (C.c_int, [_DP, _DP, _I32, _D, _D, _D, _I32, _I32, _I32P]),
@@ -289,6 +291,16 @@ def chase_filter_noalloc(A_ptr, lda, V_ptr, ldv, W_ptr, ldw, N, n, degs, c, e, m
     check(load().chase_filter_noalloc(A_ptr, lda, V_ptr, ldv, W_ptr, ldw, N, n, d, c, e, mu_1,
                                       C.byref(mv), stream), "chase_filter_noalloc")
     return mv.value
+
+
+def chase_heev(G_ptr, ldg, n, stream):
+    """Eigenvalues (ascending, numpy array) and the number of Jacobi sweeps;
+    the eigenvectors are written over G."""
+    import numpy as np
+    theta = np.zeros(n, dtype=np.float64)
+    sw = C.c_int32(0)
+    check(load().chase_heev(G_ptr, ldg, n, theta.ctypes.data_as(_DP), C.byref(sw), stream), "chase_heev")
+    return theta, sw.value
 
 
 def chase_caqr(V_ptr, ldv, N, n, cond, force, stream) -> int:

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchase_hip.so")
 
-SOURCES = ["zgemm.hip", "zfilter.hip", "zgrad.hip", "bfilter.hip", "small.hip", "hhqr.hip", "noalloc.hip", "schedule.cpp", "driver.cpp"]
+SOURCES = ["zgemm.hip", "zfilter.hip", "zgrad.hip", "bfilter.hip", "small.hip", "hhqr.hip", "heevj.hip", "noalloc.hip", "schedule.cpp", "driver.cpp"]
 ARCH = "gfx950"
 
 

@@ -224,7 +224,7 @@ struct Workspace {
   z64* hhrow = nullptr;
   double* theta = nullptr;
   double* resd = nullptr;
-  double* E = nullptr;   // heevd off-diagonal workspace
+  double* E = nullptr;   // SVD workspace of the trace's exact condition number
   double* shift = nullptr;
   int* info = nullptr;
   int* flag = nullptr;
@@ -246,6 +246,8 @@ struct Workspace {
   void* tail_ws = nullptr;     // split-K tail of the big GEMMs
   int* tail_counters = nullptr;
   z64* tune_scratch = nullptr; // autotuner output sink (N x ne), allocated on first use
+  void* jacws = nullptr;       // block-Jacobi eigensolver of the n_e x n_e quotient
+  int jac_sweeps = 0;          // sweeps of its last call
   // Real symmetric problems run on the row-pair view: a real column of even
   // length 2 N is read as N complex values (rows 2 i, 2 i + 1 as Re, Im), so
   // every column operation, and every product whose real part is the wanted
@@ -253,7 +255,6 @@ struct Workspace {
   // number of row pairs and `rows` the order; an odd order gets one zero row.
   bool real = false;
   int64_t rows = 0;
-  double* Gr = nullptr;        // ne x ne real copy for the symmetric eigensolver
   z64* Cint = nullptr;         // N x ne: the caller's block in the row-pair layout
   double* Hpad = nullptr;      // 2N x 2N copy of H when its own layout does not fit
   const double* Hr = nullptr;  // this solve's H (real, order rows) for the Lanczos products
@@ -310,6 +311,7 @@ struct Workspace {
       st = st ? st : alloc(&hhpart, (size_t)kHouseholderMaxWg * 2 * hp);
       st = st ? st : alloc(&hhrow, hp);
     }
+    st = st ? st : alloc(reinterpret_cast<char**>(&jacws), (size_t)heevj_workspace_bytes(ne));
     st = st ? st : alloc(&theta, (size_t)ne);
     st = st ? st : alloc(&resd, (size_t)ne);
     st = st ? st : alloc(&E, (size_t)ne);
@@ -359,7 +361,6 @@ struct Workspace {
     if (st) return st;
     real = true;
     rows = n_real;
-    st = st ? st : alloc(&Gr, (size_t)ne_ * ne_);
     st = st ? st : alloc(&Cint, (size_t)N * ne_);
     if (st) release();
     return st;
@@ -853,29 +854,13 @@ static int rr_project(Workspace& w, const z64* A, int64_t lda, z64* Q, int64_t l
   return zgemm_splitk(1, 0, q, w.ws, choose_splits(n, n, N, w.max_splits, true), w.real ? 3 : 2, s);
 }
 
+// The quotient's eigensolve (Alg. 2): ascending Ritz values into w.theta and
+// the eigenvectors over w.G, by the block-Jacobi kernels of heevj.hip.  The
+// real variant's quotient has zero imaginary parts, which the complex plane
+// rotations keep at zero, so its eigenvectors come out real.
 static int rr_eigensolve(Workspace& w, int64_t n, hipStream_t s) {
   if (n <= 0) return kOk;
-  int st;
-  rocblas_set_stream(w.rb, s);
-  if (w.real) {  // real symmetric quotient: eigenvectors real, back in complex storage
-    if ((st = z_real_part(w.G, n, w.Gr, n, n, s))) return st;
-    rocblas_status r = rocsolver_dsyevd(w.rb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n, w.Gr,
-                                        (rocblas_int)n, w.theta, w.E, w.info);
-    if (r != rocblas_status_success) {
-      set_msg("rocsolver_dsyevd failed");
-      return kHipError;
-    }
-    if ((st = d_to_z(w.Gr, n, w.G, n, n, s))) return st;
-  } else {
-    rocblas_status r = rocsolver_zheevd(w.rb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n,
-                                        reinterpret_cast<rocblas_double_complex*>(w.G), (rocblas_int)n, w.theta,
-                                        w.E, w.info);
-    if (r != rocblas_status_success) {
-      set_msg("rocsolver_zheevd failed");
-      return kHipError;
-    }
-  }
-  return kOk;
+  return heevj(w.G, n, n, w.theta, w.jacws, &w.jac_sweeps, s);
 }
 
 static int rr_finish(Workspace& w, z64* Q, int64_t ldq, z64* V, int64_t ldv, int64_t n, hipStream_t s) {
@@ -1297,6 +1282,8 @@ struct ProblemState {
   int post_filter(hipStream_t s) {
     int st;
     if ((st = post_filter_a(s)) || (st = rr_eigensolve(*w, na(), s))) return st;
+    S.eig_sweeps += w->jac_sweeps;
+    rec.eig_sweeps = w->jac_sweeps;
     return post_filter_b(s);
   }
 
@@ -2292,6 +2279,35 @@ int chase_rayleigh_ritz(const void* A, int64_t lda, void* Q, int64_t ldq, int64_
     }
   }
   w.release();
+  return st;
+}
+
+int chase_heev(void* G, int64_t ldg, int64_t n, double* theta, int32_t* sweeps, chase_stream_t stream) {
+  if (!G || !aligned16(G)) return -1;
+  if (ldg < n) return -2;
+  if (n < 1 || n > 65536) return -3;
+  if (!theta) return -4;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  double* th = nullptr;
+  if (hipMalloc(&ws, (size_t)heevj_workspace_bytes(n)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&th), sizeof(double) * (size_t)n) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ws) (void)hipFree(ws);
+    set_msg("chase_heev: hipMalloc failed");
+    return kAllocFailed;
+  }
+  int sw = 0;
+  int st = heevj(reinterpret_cast<z64*>(G), ldg, n, th, ws, &sw, s);
+  if (!st && (hipMemcpyAsync(theta, th, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess)) {
+    set_msg("chase_heev: copy-out failed");
+    st = kHipError;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(ws);
+  (void)hipFree(th);
+  if (sweeps) *sweeps = sw;
   return st;
 }
 

@@ -222,8 +222,6 @@ int symv_block(const double* H, int64_t ldh, const double* V, int64_t ldv, doubl
 int dcopy_pad(const double* src, int64_t lds, int64_t rows_src, int64_t cols_src, double* dst, int64_t ldd,
               int64_t rows_dst, int64_t cols_dst, hipStream_t s);
 // R = Re(G) and G = R + 0 i for n x n blocks.
-int z_real_part(const z64* G, int64_t ldg, double* R, int64_t ldr, int64_t n, hipStream_t s);
-int d_to_z(const double* R, int64_t ldr, z64* G, int64_t ldg, int64_t n, hipStream_t s);
 // A real M x n block (leading dimension ldr, in doubles) as a complex128
 // block with zero imaginary parts, and back (the real parts).
 int widen_real_block(const double* R, int64_t ldr, z64* X, int64_t ldx, int64_t M, int64_t n, hipStream_t s);
@@ -234,6 +232,14 @@ int convert_z_to_c(const z64* src, int64_t lds, c32* dst, int64_t ldd, int64_t N
                    hipStream_t s);
 int convert_c_to_z(const c32* src, int64_t lds, z64* dst, int64_t ldd, int64_t N, int64_t n,
                    hipStream_t s, double scale = 1.0);
+
+// Eigen-decomposition of the n x n Hermitian matrix G (lower triangle read,
+// leading dimension ldg) by two-sided block Jacobi (heevj.hip): ascending
+// eigenvalues into theta (device, n), eigenvectors written over G.  ws:
+// heevj_workspace_bytes(n) bytes.  Host-synchronous once per sweep; returns
+// kBreakdown for non-finite input or no convergence in 40 sweeps.
+int64_t heevj_workspace_bytes(int64_t n);
+int heevj(z64* G, int64_t ldg, int64_t n, double* theta, void* ws, int* sweeps_out, hipStream_t s);
 
 // Argument checks of chase_filter (driver.cpp): 0, or the negative status.
 int filter_check_args(const void* A, int64_t lda, const void* V, int64_t ldv, const void* W, int64_t ldw, int64_t N,

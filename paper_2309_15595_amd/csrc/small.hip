@@ -464,18 +464,6 @@ __global__ void dcopy_pad_kernel(const double* src, int64_t lds, int64_t rows_sr
   dst[m + j * ldd] = (m < rows_src && j < cols_src) ? src[m + j * lds] : 0.0;
 }
 
-// R = Re(G) and G = R + 0i for n x n blocks.
-__global__ void z_real_part_kernel(const zv* G, int64_t ldg, double* R, int64_t ldr, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t j = blockIdx.y;
-  if (i < n) R[i + j * ldr] = G[i + j * ldg].re;
-}
-__global__ void d_to_z_kernel(const double* R, int64_t ldr, zv* G, int64_t ldg, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t j = blockIdx.y;
-  if (i < n) G[i + j * ldg] = zv{R[i + j * ldr], 0.0};
-}
-
 // ---- counter-based Gaussian fill (splitmix64 + Box-Muller) ------------------
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -706,22 +694,6 @@ int dcopy_pad(const double* src, int64_t lds, int64_t rows_src, int64_t cols_src
   if (rows_dst <= 0 || cols_dst <= 0) return kOk;
   hipLaunchKernelGGL(dcopy_pad_kernel, dim3((unsigned)cdiv(rows_dst, 256), (unsigned)cols_dst), dim3(256), 0, s,
                      src, lds, rows_src, cols_src, dst, ldd, rows_dst);
-  CHASE_CHK_LAUNCH();
-  return kOk;
-}
-
-int z_real_part(const z64* G, int64_t ldg, double* R, int64_t ldr, int64_t n, hipStream_t s) {
-  if (n <= 0) return kOk;
-  hipLaunchKernelGGL(z_real_part_kernel, dim3((unsigned)cdiv(n, 256), (unsigned)n), dim3(256), 0, s,
-                     reinterpret_cast<const zv*>(G), ldg, R, ldr, n);
-  CHASE_CHK_LAUNCH();
-  return kOk;
-}
-
-int d_to_z(const double* R, int64_t ldr, z64* G, int64_t ldg, int64_t n, hipStream_t s) {
-  if (n <= 0) return kOk;
-  hipLaunchKernelGGL(d_to_z_kernel, dim3((unsigned)cdiv(n, 256), (unsigned)n), dim3(256), 0, s, R, ldr,
-                     reinterpret_cast<zv*>(G), ldg, n);
   CHASE_CHK_LAUNCH();
   return kOk;
 }

@@ -115,21 +115,25 @@ def test_workspace_bytes_memory_model():
     """Eq. (2) at p = q = 1 on the host, with no device call.  Eq. (2) counts
     N^2 + 4 N n_e + n_e^2 words; the caller holds H and V (N^2 + N n_e), the
     library C2 and B (2 N n_e), three n_e x n_e matrices plus the 16 split-K
-    partials of the n_e x n_e products (19 n_e^2), a fixed 256 MiB of filter
-    split-K tail partials and O(N + n_e) vectors.  Each option adds exactly
-    what it documents."""
+    partials of the n_e x n_e products (19 n_e^2), the block-Jacobi
+    eigensolver's working matrix and eigenvector accumulator (2 n_p^2, n_p =
+    n_e rounded up to a multiple of 32), a fixed 256 MiB of filter split-K
+    tail partials and O(N + n_e) vectors.  Each option adds exactly what it
+    documents."""
     L = _lib()
     lib = L.load()
     z = 16
     tail = 256 << 20
     for N, nev, nex in [(20000, 1000, 300), (5000, 200, 60), (1201, 90, 30)]:
         ne = nev + nex
+        npad = 32 * -(-ne // 32)
         fp64 = L.chase_workspace_bytes(N, L.default_params(nev=nev, nex=nex), 0)
-        core = z * (2 * N * ne + 19 * ne * ne) + tail
+        core = z * (2 * N * ne + 19 * ne * ne + 2 * npad * npad) + tail
         assert core <= fp64 <= core + z * (64 * N + 128 * ne) + (1 << 20)
-        # one N x n_e block fewer than Eq. (2), 18 n_e^2 words and the tail more
+        # one N x n_e block fewer than Eq. (2); 18 n_e^2 + 2 n_p^2 words and the tail more
         eq2 = z * (N * N + 4 * N * ne + ne * ne)
-        assert z * (N * N + N * ne) + fp64 <= eq2 - z * N * ne + z * 18 * ne * ne + tail + z * (64 * N + 128 * ne) + (1 << 20)
+        assert z * (N * N + N * ne) + fp64 <= (eq2 - z * N * ne + z * (18 * ne * ne + 2 * npad * npad) + tail
+                                               + z * (64 * N + 128 * ne) + (1 << 20))
         fp32 = L.chase_workspace_bytes(N, L.default_params(nev=nev, nex=nex, precision=L.CHASE_FP32_MIXED), 0)
         assert fp32 - fp64 == 8 * N * N + 2 * 8 * N * ne     # complex64 H and two complex64 blocks
         bf16 = L.chase_workspace_bytes(N, L.default_params(nev=nev, nex=nex, precision=L.CHASE_BF16X3_MIXED), 0)
