@@ -3,9 +3,10 @@
 // degree optimisation, CondEst, locking decisions) and the C ABI.
 //
 // Device work all runs in the hand-written kernels of zgemm.hip, zfilter.hip,
-// bfilter.hip, zgrad.hip, hhqr.hip and small.hip, except the n_e x n_e
-// eigensolve of Rayleigh-Ritz (rocSOLVER zheevd / dsyevd) and the trace's
-// singular values (rocSOLVER zgesvd / dgesvd, studies only).  The real type
+// bfilter.hip, zgrad.hip, hhqr.hip, heevj.hip and small.hip, except the
+// level-2 trace's singular values (rocSOLVER zgesvd / dgesvd, studies only).
+// The n_e x n_e eigensolve of Rayleigh-Ritz is the block Jacobi of heevj.hip;
+// the real quotient (zero imaginary parts) gets real eigenvectors from it.  The real type
 // variant's Householder QR runs the complex hhqr.hip kernels on its block
 // widened to complex128 with zero imaginary parts.
 //
