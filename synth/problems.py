@@ -185,7 +185,12 @@ def hermitian_from_spectrum_torch(lam: np.ndarray, seed: int = SEED_Q,
     for r0 in range(0, N, chunk):
         r1 = min(N, r0 + chunk)
         out[r0:r1, :] = torch.fft.ifft(out[r0:r1, :], dim=1, norm="ortho")
-    # Hermitise in place, tile pairs (i, j) and (j, i) together
+    # Hermitise: (A + A^H) / 2 entry by entry (the same arithmetic either way);
+    # in one pass when a transposed copy fits comfortably, else in place by
+    # tile pairs (i, j) and (j, i)
+    if N <= 24000:
+        out.add_(out.conj().T.contiguous()).mul_(0.5)
+        return out
     for r0 in range(0, N, chunk):
         r1 = min(N, r0 + chunk)
         for k0 in range(r0, N, chunk):
