@@ -171,8 +171,13 @@ def hermitian_from_spectrum_torch(lam: np.ndarray, seed: int = SEED_Q,
     phi_np = np.exp(2j * np.pi * rng.random(N))
     c = torch.from_numpy(_circulant_first_column(lam)).to(device)
     phi = torch.from_numpy(phi_np).to(device)
-    out = torch.empty((N, N), dtype=torch.complex128, device=device)
     rows = torch.arange(N, device=device)
+    if N <= 16384:
+        # the same three steps on whole matrices (a few N^2 buffers)
+        M = c[torch.remainder(rows[:, None] - rows[None, :], N)] * phi[:, None] * phi.conj()[None, :]
+        M = torch.fft.ifft(torch.fft.fft(M, dim=0, norm="ortho"), dim=1, norm="ortho")
+        return M.add_(M.conj().T.contiguous()).mul_(0.5)
+    out = torch.empty((N, N), dtype=torch.complex128, device=device)
     # column blocks: M[:, blk] -> F M[:, blk] (FFT along rows index)
     for k0 in range(0, N, chunk):
         k1 = min(N, k0 + chunk)
@@ -185,12 +190,7 @@ def hermitian_from_spectrum_torch(lam: np.ndarray, seed: int = SEED_Q,
     for r0 in range(0, N, chunk):
         r1 = min(N, r0 + chunk)
         out[r0:r1, :] = torch.fft.ifft(out[r0:r1, :], dim=1, norm="ortho")
-    # Hermitise: (A + A^H) / 2 entry by entry (the same arithmetic either way);
-    # in one pass when a transposed copy fits comfortably, else in place by
-    # tile pairs (i, j) and (j, i)
-    if N <= 24000:
-        out.add_(out.conj().T.contiguous()).mul_(0.5)
-        return out
+    # Hermitise in place, tile pairs (i, j) and (j, i) together
     for r0 in range(0, N, chunk):
         r1 = min(N, r0 + chunk)
         for k0 in range(r0, N, chunk):
