@@ -1951,13 +1951,22 @@ int chase_solve_batched(int32_t count, const int64_t* Ns, const void* const* As,
     }
     // Fill the table with this iteration's filter GEMMs (plans) for tile
     // configuration cfg, with the running tile count of every step.
+    // Problems enter each step's row longest first (largest order: its tiles
+    // have the longest K loop), for the grouped kernel's rotation over XCDs.
     std::vector<std::vector<GemmArgs>> plans(count);
+    std::vector<int> slot_of(count);
+    {
+      std::vector<int> by_len(count);
+      std::iota(by_len.begin(), by_len.end(), 0);
+      std::stable_sort(by_len.begin(), by_len.end(), [&](int x, int y) { return Ns[x] > Ns[y]; });
+      for (int j = 0; j < count; ++j) slot_of[by_len[j]] = j;
+    }
     auto build_table = [&](int cfg) -> int {
       std::memset(h_table, 0, tbytes);
       for (int i = 0; i < count; ++i) {
         if (plans[i].size() > (size_t)max_deg) return -11;
         for (size_t k = 0; k < plans[i].size(); ++k) {
-          GroupEntry& e = h_table[k * count + i];
+          GroupEntry& e = h_table[k * count + slot_of[i]];
           e.g = plans[i][k];
           zfilter_tiles(e.g.M, e.g.N, &e.tiles_n, cfg);
         }

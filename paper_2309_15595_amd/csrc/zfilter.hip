@@ -822,13 +822,16 @@ __device__ __forceinline__ void zdma_grouped_body(const GroupEntry* __restrict__
   t.full = row[count - 1].tile_end;
   t.ksplit = 1;
   t.queue = queue;
-  TileOrder all;
-  all.tiles_m = t.full;
-  all.tiles_n = 1;
-  all.edge_last = false;
-  const QueueShare q = queue_share(t, all);
+  // Tiles are dealt to the XCDs in rotation (tile i to XCD i % 8): the table
+  // lists the problems longest first, so every XCD gets the same mix of long
+  // and short tiles, each longest first.  (Contiguous shares would give one
+  // XCD the largest problems' tiles.)  No L2 reuse is lost that matters: a
+  // tile's operands at 32 flop per byte stay well inside HBM's rate.
+  const int xcd = (int)(blockIdx.x % 8);
+  const int64_t mine = t.full > xcd ? (t.full - xcd + 7) / 8 : 0;
   int p = 0;
-  for (int64_t i; (i = queue_next(t, q, &item)) >= 0;) {
+  for (int64_t it; (it = wg_fetch_add(queue + xcd, 1, &item)) < mine;) {
+    const int64_t i = xcd + 8 * it;
     while (row[p].tile_end <= i) ++p;  // items arrive in increasing order
     p = __builtin_amdgcn_readfirstlane(p);
     const int64_t begin = p > 0 ? row[p - 1].tile_end : 0;
