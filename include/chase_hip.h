@@ -74,7 +74,7 @@ typedef struct {
   double tol;           /* residual threshold relative to ||H|| (1e-10) */
   double b_sup, mu_1, mu_ne, norm_est;
   double mixed_switch;  /* FP32 -> FP64 switch at resd <= mixed_switch * ||H|| (5e-6) */
-  double bf16_switch;   /* BF16x3 -> FP32 switch at resd <= bf16_switch * ||H|| (2e-5) */
+  double bf16_switch;   /* BF16x3 -> FP32 switch at resd <= bf16_switch * ||H|| (5e-5) */
   uint64_t seed;        /* generator of the initial block / Lanczos starts when
                            the caller supplies none */
 } chase_params_t;

@@ -1523,7 +1523,7 @@ int chase_default_params(chase_params_t* p) {
   p->bounds_given = 0;
   p->tol = 1e-10;
   p->mixed_switch = 5e-6;
-  p->bf16_switch = 2e-5;
+  p->bf16_switch = 5e-5;
   p->seed = 2309;
   return 0;
 }
