@@ -124,8 +124,9 @@ int chase_create(int64_t N, const chase_params_t* p, chase_handle_t* h);
  *            (N+1)^2 doubles on first use, and its first Householder QR
  *            two N x n_e and one N x 32 complex128 blocks), 2: chase_create_c64
  *   bytes    (host) out
- * Not counted: the rocBLAS handle's own device-memory pool, which rocSOLVER's
- * eigensolver and QR calls grow on demand (of order n_e^2 words).
+ * Not counted: the buffers of the level-2 trace, allocated on its first use
+ * (an N x n_e copy of the block, and 2 (2 n_e)^2 + 5 n_e^2 words for the
+ * singular values of its R).
  * Returns -1 for N < 2, -2 for invalid params (or a precision the variant
  * does not offer), -3 for an unknown variant, -4 for a null bytes. */
 int chase_workspace_bytes(int64_t N, const chase_params_t* p, int32_t variant, int64_t* bytes);
@@ -360,9 +361,11 @@ typedef struct {
 
 /* Trace the next chase_solve calls on h: level 0 off (default), 1 records a
  * chase_trace_t per outer iteration, 2 also computes the kappa_com figures
- * from singular values of the block before each CAQR (rocSOLVER SVDs of an
- * N x n_e copy: expensive, for studies only; the copy uses the handle's
- * workspace and does not change the iteration).  At most CHASE_TRACE_MAX
+ * from singular values of the block before each CAQR (Householder QR of an
+ * N x n_e copy, then the singular values of R as the eigenvalues of
+ * [[0, R], [R^H, 0]] by the block-Jacobi eigensolver: expensive, for studies
+ * only; the buffers are allocated on the first such solve and the iteration
+ * is not changed).  At most CHASE_TRACE_MAX
  * iterations are kept.  Returns -1 for a null handle, -2 for a bad level. */
 int chase_set_trace(chase_handle_t h, int32_t level);
 

@@ -3,10 +3,11 @@
 // degree optimisation, CondEst, locking decisions) and the C ABI.
 //
 // Device work all runs in the hand-written kernels of zgemm.hip, zfilter.hip,
-// bfilter.hip, zgrad.hip, hhqr.hip, heevj.hip and small.hip, except the
-// level-2 trace's singular values (rocSOLVER zgesvd / dgesvd, studies only).
-// The n_e x n_e eigensolve of Rayleigh-Ritz is the block Jacobi of heevj.hip;
-// the real quotient (zero imaginary parts) gets real eigenvectors from it.  The real type
+// bfilter.hip, zgrad.hip, hhqr.hip, heevj.hip and small.hip; the library
+// links no BLAS or LAPACK.  The n_e x n_e eigensolve of Rayleigh-Ritz is the
+// block Jacobi of heevj.hip (the real quotient, with zero imaginary parts,
+// gets real eigenvectors from it), and so are the level-2 trace's singular
+// values (of the Householder R, through [[0, R], [R^H, 0]]).  The real type
 // variant's Householder QR runs the complex hhqr.hip kernels on its block
 // widened to complex128 with zero imaginary parts.
 //
@@ -18,8 +19,6 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <atomic>
@@ -225,7 +224,6 @@ struct Workspace {
   z64* hhrow = nullptr;
   double* theta = nullptr;
   double* resd = nullptr;
-  double* E = nullptr;   // SVD workspace of the trace's exact condition number
   double* shift = nullptr;
   int* info = nullptr;
   int* flag = nullptr;
@@ -266,7 +264,6 @@ struct Workspace {
   bool c64 = false;
   const c32* H32 = nullptr;    // this solve's H
   int64_t ldh32 = 0;
-  rocblas_handle rb = nullptr;
   std::vector<void*> owned;
   // Sizing mode: alloc adds up the bytes and allocates nothing; create()
   // then makes no device call either.
@@ -315,7 +312,6 @@ struct Workspace {
     st = st ? st : alloc(reinterpret_cast<char**>(&jacws), (size_t)heevj_workspace_bytes(ne));
     st = st ? st : alloc(&theta, (size_t)ne);
     st = st ? st : alloc(&resd, (size_t)ne);
-    st = st ? st : alloc(&E, (size_t)ne);
     st = st ? st : alloc(&shift, 1);
     st = st ? st : alloc(&info, 1);
     st = st ? st : alloc(&flag, 1);
@@ -347,10 +343,6 @@ struct Workspace {
         set_msg("hipMemset failed");
         st = kHipError;
       }
-    }
-    if (!st && !counting && rocblas_create_handle(&rb) != rocblas_status_success) {
-      set_msg("rocblas_create_handle failed");
-      st = kHipError;
     }
     if (st) release();
     return st;
@@ -400,6 +392,29 @@ struct Workspace {
     owned.erase(std::remove(owned.begin(), owned.end(), *p), owned.end());
     *p = nullptr;
   }
+  // Trace level 2 (first use): a copy of the block to factor, its R, the
+  // augmented 2 n_e x 2 n_e Hermitian matrix of R and its eigensolver's
+  // workspace and eigenvalues
+  z64* trX = nullptr;
+  z64* trR = nullptr;
+  z64* trAug = nullptr;
+  void* trJac = nullptr;
+  double* trTheta = nullptr;
+  int ensure_trace() {
+    if (trX && trR && trAug && trJac && trTheta) return kOk;
+    const size_t n2 = 2 * (size_t)ne;
+    int st = trX ? kOk : alloc(&trX, (size_t)N * ne);
+    st = st ? st : (trR ? kOk : alloc(&trR, (size_t)ne * ne));
+    st = st ? st : (trAug ? kOk : alloc(&trAug, n2 * n2));
+    st = st ? st : (trJac ? kOk : alloc(reinterpret_cast<char**>(&trJac), (size_t)heevj_workspace_bytes((int64_t)n2)));
+    st = st ? st : (trTheta ? kOk : alloc(&trTheta, n2));
+    if (st) {
+      for (void** q : {reinterpret_cast<void**>(&trX), reinterpret_cast<void**>(&trR), reinterpret_cast<void**>(&trAug),
+                       &trJac, reinterpret_cast<void**>(&trTheta)})
+        free_one(q);
+    }
+    return st;
+  }
   int ensure_hpad() {
     return Hpad ? kOk : alloc(&Hpad, (size_t)(2 * N) * (size_t)(2 * N));
   }
@@ -407,8 +422,6 @@ struct Workspace {
   void release() {
     for (void* p : owned) (void)hipFree(p);
     owned.clear();
-    if (rb) rocblas_destroy_handle(rb);
-    rb = nullptr;
   }
 };
 
@@ -747,7 +760,7 @@ static int cholqr_pass(Workspace& w, z64* X, int64_t ldx, int64_t n, bool shifte
   return chol_apply(w, X, ldx, n, shifted, failed, s);
 }
 
-static int householder(Workspace& w, z64* X, int64_t ldx, int64_t n, hipStream_t s) {
+static int householder(Workspace& w, z64* X, int64_t ldx, int64_t n, hipStream_t s, z64* R_out = nullptr) {
   HouseholderWs h;
   h.V = w.hhV;
   h.T = w.hhT;
@@ -758,6 +771,7 @@ static int householder(Workspace& w, z64* X, int64_t ldx, int64_t n, hipStream_t
   h.tau = w.tau;
   h.Q = w.B;
   h.splitk = w.ws;
+  h.R = R_out;
   if (!w.real) return householder_qr(X, ldx, w.N, n, h, s);
   // The real block (2N rows; a zero padding row stays zero) through the same
   // kernels, widened with zero imaginary parts: every norm, reflector, tau and
@@ -983,10 +997,11 @@ static bool valid_params(const chase_params_t* p) {
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 // Exact condition number sigma_max / sigma_min of the N x n block X (trace
-// level 2): singular values of a copy in the workspace (rocSOLVER SVD, no
-// vectors).  With `equilibrate` the copy's columns are scaled to unit norm
-// first.  w.B holds the copy; w.theta, w.E and w.resd serve as scratch, all
-// free between the filter and the QR.
+// level 2): X (or X with unit columns) is copied and factored by Householder
+// QR; the singular values of R are the non-negative eigenvalues of the
+// Hermitian [[0, R], [R^H, 0]], found by the block-Jacobi eigensolver (to
+// within a few ulps of sigma_max, as an SVD's).  w.theta and w.resd serve as
+// scratch for the column norms; w.B holds Q.
 static int kappa_of_block(Workspace& w, const z64* X, int64_t ldx, int64_t n, bool equilibrate, hipStream_t s,
                           double* kappa) {
   int st = kOk;
@@ -994,6 +1009,7 @@ static int kappa_of_block(Workspace& w, const z64* X, int64_t ldx, int64_t n, bo
     *kappa = std::nan("");
     return kOk;
   }
+  if ((st = w.ensure_trace())) return st;
   if (equilibrate) {
     std::vector<double> g(n, 0.0);
     CHASE_CHK(hipMemcpyAsync(w.theta, g.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
@@ -1002,31 +1018,20 @@ static int kappa_of_block(Workspace& w, const z64* X, int64_t ldx, int64_t n, bo
     CHASE_CHK(hipStreamSynchronize(s));
     for (double& v : g) v = v > 0 ? 1.0 / v : 0.0;
     CHASE_CHK(hipMemcpyAsync(w.theta, g.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-    if ((st = scale_columns(X, ldx, w.theta, w.B, w.N, w.N, n, s))) return st;
+    if ((st = scale_columns(X, ldx, w.theta, w.trX, w.N, w.N, n, s))) return st;
     CHASE_CHK(hipStreamSynchronize(s));  // g is read by the copy before it goes
-  } else if ((st = copy_columns(X, ldx, w.B, w.N, w.N, n, s))) {
+  } else if ((st = copy_columns(X, ldx, w.trX, w.N, w.N, n, s))) {
     return st;
   }
-  rocblas_set_stream(w.rb, s);
-  rocblas_status r =
-      w.real ? rocsolver_dgesvd(w.rb, rocblas_svect_none, rocblas_svect_none, (rocblas_int)(2 * w.N),
-                                (rocblas_int)n, reinterpret_cast<double*>(w.B), (rocblas_int)(2 * w.N), w.theta,
-                                nullptr, 1, nullptr, 1, w.E, rocblas_inplace, w.info)
-             : rocsolver_zgesvd(w.rb, rocblas_svect_none, rocblas_svect_none, (rocblas_int)w.N, (rocblas_int)n,
-                                reinterpret_cast<rocblas_double_complex*>(w.B), (rocblas_int)w.N, w.theta, nullptr,
-                                1, nullptr, 1, w.E, rocblas_inplace, w.info);
-  if (r != rocblas_status_success) {
-    set_msg("rocsolver_zgesvd failed");
-    return kHipError;
-  }
-  std::vector<double> sv(n);
-  CHASE_CHK(hipMemcpyAsync(sv.data(), w.theta, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  if ((st = householder(w, w.trX, w.N, n, s, w.trR))) return st;
+  if ((st = augment_hermitian(w.trR, n, w.trAug, s))) return st;
+  int sweeps = 0;
+  if ((st = heevj(w.trAug, 2 * n, 2 * n, w.trTheta, w.trJac, &sweeps, s))) return st;
+  std::vector<double> ev(2 * n);
+  CHASE_CHK(hipMemcpyAsync(ev.data(), w.trTheta, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
   CHASE_CHK(hipStreamSynchronize(s));
-  double lo = sv[0], hi = sv[0];
-  for (double v : sv) {
-    lo = std::min(lo, v);
-    hi = std::max(hi, v);
-  }
+  // ascending: -sigma_1 .. -sigma_n, sigma_n .. sigma_1
+  const double hi = ev[2 * n - 1], lo = std::fabs(ev[n]);
   *kappa = lo > 0 ? hi / lo : std::numeric_limits<double>::infinity();
   return kOk;
 }

@@ -217,7 +217,36 @@ int reflector_workgroups(int64_t rows) {
   return (int)(g < 1 ? 1 : (g > kHouseholderMaxWg ? kHouseholderMaxWg : g));
 }
 
+// R[r][c] = A[r][c] for r <= c, 0 below (n x n, leading dimension n).
+__global__ void hh_copy_r(const zv* A, int64_t ldx, int64_t n, zv* R) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (r < n) R[r + c * n] = r <= c ? A[r + c * ldx] : zv{0.0, 0.0};
+}
+
+// Aug (2n x 2n, leading dimension 2n) = [[0, R], [R^H, 0]]: entry (n + i, j)
+// = conj(R[j][i]), entry (j, n + i) = R[j][i], zero elsewhere.
+__global__ void hh_augment(const zv* R, int64_t n, zv* Aug) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (r >= 2 * n) return;
+  zv v{0.0, 0.0};
+  if (r >= n && c < n) {
+    const zv x = R[c + (r - n) * n];
+    v = zv{x.re, -x.im};
+  } else if (r < n && c >= n) {
+    v = R[r + (c - n) * n];
+  }
+  Aug[r + c * 2 * n] = v;
+}
+
 }  // namespace
+
+int augment_hermitian(const z64* R, int64_t n, z64* Aug, hipStream_t s) {
+  if (n <= 0) return kOk;
+  hipLaunchKernelGGL(hh_augment, dim3((unsigned)cdiv(2 * n, 256), (unsigned)(2 * n)), dim3(256), 0, s,
+                     reinterpret_cast<const zv*>(R), n, reinterpret_cast<zv*>(Aug));
+  CHASE_CHK_LAUNCH();
+  return kOk;
+}
 
 int householder_qr(z64* X, int64_t ldx, int64_t M, int64_t n, const HouseholderWs& ws, hipStream_t s) {
   if (n <= 0) return kOk;
@@ -274,6 +303,11 @@ int householder_qr(z64* X, int64_t ldx, int64_t M, int64_t n, const HouseholderW
     c.Y = X + j0 + jend * ldx; c.ldy = ldx;
     c.alpha = -1.0; c.beta = 1.0;
     if ((st = zgemm_launch(0, 0, c, s))) return st;
+  }
+  if (ws.R) {  // R: the upper triangle of the factored block
+    hipLaunchKernelGGL(hh_copy_r, dim3((unsigned)cdiv(n, 256), (unsigned)n), dim3(256), 0, s, A, ldx, n,
+                       reinterpret_cast<zv*>(ws.R));
+    CHASE_CHK_LAUNCH();
   }
   // Q = H_1 ... H_npan [I; 0], accumulated backwards; panel p only changes
   // rows and columns from j0 on

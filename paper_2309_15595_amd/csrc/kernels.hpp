@@ -170,8 +170,14 @@ struct HouseholderWs {
   z64* tau = nullptr;     // n
   z64* Q = nullptr;       // M x n (leading dimension M)
   z64* splitk = nullptr;  // split-K partials: 16 x panel x n
+  z64* R = nullptr;       // optional n x n output (leading dimension n): the R factor, zero below the diagonal
 };
 int householder_qr(z64* X, int64_t ldx, int64_t M, int64_t n, const HouseholderWs& ws, hipStream_t s);
+
+// The 2n x 2n Hermitian [[0, R], [R^H, 0]] of an n x n R (lower triangle
+// written: the R^H block; the diagonal blocks zero), whose eigenvalues are
+// the singular values of R and their negatives.
+int augment_hermitian(const z64* R, int64_t n, z64* Aug, hipStream_t s);
 
 // ---- small dense kernels (small.hip) --------------------------------------
 // Blocked lower Cholesky G = L L^H in place (lower part), n x n, ld.

@@ -1,7 +1,7 @@
 """One-GPU versions of the paper's two QR experiments (Sec. 4.2 and 4.3).
 
   * Condition numbers (the comparison of Fig. 1): every iteration's estimate
-    from Alg. 5 beside exact condition numbers (SVDs) of the block 1D-CAQR
+    from Alg. 5 beside exact condition numbers (singular values) of the block 1D-CAQR
     receives, of its filtered columns alone and of the block with unit
     columns, with and without degree optimisation.
   * QR variants (the comparison of Table 2): time to solution, QR time,
@@ -76,7 +76,7 @@ def main(argv=None):
             name = "opt" if opt else "no-opt"
             out["kappa"][name] = {"converged": bool(info.converged), "iterations": info.stats["iterations"],
                                   "trace": tr}
-            print(f"condition numbers, {name} ({dt:.1f} s with the SVDs):", flush=True)
+            print(f"condition numbers, {name} ({dt:.1f} s with the singular values):", flush=True)
             print("  it  locked   kappa_est   com:whole   com:active   com:equil  est/active  QR", flush=True)
             for t in tr:
                 ratio = t["kappa_est"] / t["kappa_com_active"]

@@ -173,9 +173,15 @@ def hermitian_from_spectrum_torch(lam: np.ndarray, seed: int = SEED_Q,
     phi = torch.from_numpy(phi_np).to(device)
     rows = torch.arange(N, device=device)
     if N <= 16384:
-        # the same three steps on whole matrices (a few N^2 buffers)
+        # the same steps on whole matrices, the two unitary DFTs as products
+        # with the explicit DFT matrix (a transform length per problem would
+        # each cost the FFT library a kernel build); a few N^2 buffers
+        jk = torch.remainder(rows[:, None] * rows[None, :], N).to(torch.float64)
+        F = torch.polar(torch.full_like(jk, 1.0 / np.sqrt(N)), jk * (-2.0 * np.pi / N))
+        del jk
         M = c[torch.remainder(rows[:, None] - rows[None, :], N)] * phi[:, None] * phi.conj()[None, :]
-        M = torch.fft.ifft(torch.fft.fft(M, dim=0, norm="ortho"), dim=1, norm="ortho")
+        M = (F @ M) @ F.conj()
+        del F
         return M.add_(M.conj().T.contiguous()).mul_(0.5)
     out = torch.empty((N, N), dtype=torch.complex128, device=device)
     # column blocks: M[:, blk] -> F M[:, blk] (FFT along rows index)

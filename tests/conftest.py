@@ -25,3 +25,18 @@ def parity_oracle(parity_problem):
     p = parity_problem
     return oracle.chase(p.A, oracle.Params(nev=p.nev, nex=p.nex, deg=p.deg, tol=p.tol),
                         V0=p.V0, starts=p.starts)
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _release_device_cache():
+    """Give torch's cached device blocks back after every test module, so the
+    process holds little device memory when it exits (the next process on the
+    GPU starts while the driver is still reclaiming what this one freed)."""
+    yield
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+    except Exception:
+        pass

@@ -494,7 +494,7 @@ def test_trace_condition_numbers(L, parity_problem, opt):
         if t["locked"] == 0:
             assert t["kappa_est"] >= t["kappa_com"] * (1 - 1e-8), t
     # the same iterations as the oracle while the locking agrees: the estimate
-    # is a closed form of the Ritz values and bounds, the kappa_2 figures SVDs
+    # is a closed form of the Ritz values and bounds, the kappa_2 figures singular values
     # of blocks equal to ~1e-11; the branch of Alg. 4 follows
     same = 0
     for i, t in enumerate(tr):

@@ -151,7 +151,7 @@ def test_real_solve_forced_qr_variants(L, force):
 
 def test_real_solve_random_start_and_trace(L):
     """Library-drawn start block and Lanczos starts (odd order: the padding
-    row must stay zero), and the trace's SVD on the real block."""
+    row must stay zero), and the trace's singular values of the real block."""
     from paper_2309_15595_amd.api import Solver
     p = synth.make_problem(301, 12, 6, spectrum="uniform", seed=9, real=True)
     with Solver(p.N, p.nev, p.nex, dtype=torch.float64) as s:
