@@ -279,9 +279,13 @@ struct Workspace {
       *p = nullptr;
       return kOk;
     }
-    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    const hipError_t err = hipMalloc(&q, count * sizeof(T));
+    if (err != hipSuccess) {
       (void)hipGetLastError();
-      set_msg("hipMalloc failed");
+      size_t free_b = 0, total_b = 0;
+      (void)hipMemGetInfo(&free_b, &total_b);
+      set_msg("hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed (" + hipGetErrorString(err) +
+              "; " + std::to_string(free_b >> 20) + " of " + std::to_string(total_b >> 20) + " MiB free)");
       return kAllocFailed;
     }
     owned.push_back(q);
