@@ -62,7 +62,9 @@ typedef struct {
   int32_t nex;          /* search-space increment, >= 0, nev + nex < N */
   int32_t deg;          /* initial filter degree, even, >= 2 (20) */
   int32_t max_deg;      /* cap on optimised degrees, even (36) */
-  int32_t deg_extra;    /* margin added by degree optimisation (2) */
+  int32_t deg_extra;    /* margin added by degree optimisation, even; negative
+                           (default -1): 4 when every column is filtered in
+                           FP64, 2 on the FP32 / BF16x3 ladders and complex64 */
   int32_t max_iter;     /* MaxIter (25) */
   int32_t opt;          /* 1 = per-vector degree optimisation (1) */
   int32_t precision;    /* CHASE_FP64, CHASE_FP32_MIXED or CHASE_BF16X3_MIXED */

@@ -1124,6 +1124,10 @@ struct ProblemState {
     nev = P.nev;
     ne = P.nev + P.nex;
     mixed = P.precision != CHASE_FP64 || w->c64;
+    // degree-optimisation margin: a negative value asks for the measured
+    // default of the ladder (4 with every column in FP64, 2 with FP32 or
+    // BF16x3 rungs)
+    if (P.deg_extra < 0) P.deg_extra = mixed ? 2 : 4;
     std::memset(&S, 0, sizeof(S));
     if (!use_v0 && (st = fill_gaussian(V, ldv, N, ne, P.seed, s))) return st;
     if (!use_v0 && (st = zero_pad_row(V, ldv, ne, s))) return st;
@@ -1523,7 +1527,7 @@ int chase_default_params(chase_params_t* p) {
   p->nex = 0;
   p->deg = 20;
   p->max_deg = 36;
-  p->deg_extra = 2;
+  p->deg_extra = -1;
   p->max_iter = 25;
   p->opt = 1;
   p->precision = CHASE_FP64;
