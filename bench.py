@@ -21,12 +21,15 @@ oracle's whole time to solution on the N = 800 parity workload.
 """
 from __future__ import annotations
 
+import time
+
+T_PROCESS = time.perf_counter()
+
 import argparse
 import hashlib
 import json
 import os
 import sys
-import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -51,8 +54,8 @@ def parse_args():
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 solve")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-problem batched workload")
     ap.add_argument("--mixed-runs", type=int, default=3, help="timed solves per mixed ladder (median)")
-    ap.add_argument("--budget-s", type=float, default=380.0,
-                    help="skip the batched workload when the run has already taken this long")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="skip the batched workload when the run (from process start) has taken this long")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -234,7 +237,6 @@ def main():
     from paper_2309_15595_amd.api import Solver
 
     L.load()
-    t_start = time.perf_counter()
     N, nev, nex = args.N, args.nev, args.nex
     ne = nev + nex
     dev = torch.device("cuda:0")
@@ -341,13 +343,6 @@ def main():
                 "iterations": mst["iterations"]}
             log(args, f"mixed {name}: median {np.median(mtts):.2f} s of {len(mtts)}")
 
-    if not args.no_batched:
-        elapsed = time.perf_counter() - t_start
-        if elapsed > args.budget_s:
-            out["batched"] = {"skipped": f"the run had taken {elapsed:.0f} s (budget {args.budget_s:.0f} s)"}
-        else:
-            out["batched"] = batched_leg(args)
-
     if not args.no_c64:
         # the complex64 variant on the same matrix rounded to complex64, at a
         # tolerance its FP32 products reach (about sqrt(N) u_32 ||H||)
@@ -427,6 +422,15 @@ def main():
         out["parity"]["host_sampled_resid_over_normA"] = r_host
         out["cpu_baseline"] = cpu_baseline(A_host, V0_host, args)
         log(args, f"cpu baseline: {out['cpu_baseline']['value']:.3f} TFLOP/s")
+
+    if not args.no_batched:
+        # last, and only while the whole run (from process start, imports
+        # included) stays well inside a 600 s limit: the leg takes about 110 s
+        elapsed = time.perf_counter() - T_PROCESS
+        if elapsed > args.budget_s:
+            out["batched"] = {"skipped": f"the run had taken {elapsed:.0f} s (budget {args.budget_s:.0f} s)"}
+        else:
+            out["batched"] = batched_leg(args)
     print(json.dumps(out), flush=True)
 
 

@@ -33,8 +33,9 @@ def _free():
 @pytest.mark.parametrize("variant,prec", [(0, "fp64"), (0, "fp32"), (0, "bf16x3"), (1, "fp64"), (2, "fp64")])
 def test_create_allocates_the_counted_bytes(L, variant, prec):
     """Every buffer is one hipMalloc rounded up to the allocator's page, and
-    the rocBLAS handle may reserve a pool of its own: the drop in free memory
-    lies between the count and the count plus 256 MiB, and destroy returns it."""
+    the HIP runtime may reserve memory of its own on the handle's first
+    launches: the drop in free memory lies between the count and the count
+    plus 256 MiB, and destroy returns it."""
     code = {"fp64": L.CHASE_FP64, "fp32": L.CHASE_FP32_MIXED, "bf16x3": L.CHASE_BF16X3_MIXED}[prec]
     N = 12001 if variant == 1 else 12000
     prm = L.default_params(nev=500, nex=100, precision=code)
