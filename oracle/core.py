@@ -363,6 +363,12 @@ def degree_opt(resd: np.ndarray, Lam: np.ndarray, c: float, e: float,
     return out
 
 
+def degree_order(degs: np.ndarray) -> np.ndarray:
+    """R8 (Alg. 1's sort by degree): the stable ascending permutation of the
+    active columns by degree, equal degrees keeping their current order."""
+    return np.argsort(degs, kind="stable")
+
+
 def lock_order(resd_active: np.ndarray, n_lockable: int, tol_abs: float):
     """R7: permutation of the active block moving converged pairs first."""
     n = resd_active.shape[0]
@@ -443,7 +449,7 @@ def chase(A: np.ndarray, params: Params, V0: Optional[np.ndarray] = None,
             if params.opt:
                 degs[locked:] = degree_opt(resd[locked:], Lam[locked:], c, e, tol_abs,
                                            params.max_deg, params.deg_extra)
-            order = np.argsort(degs[locked:], kind="stable")
+            order = degree_order(degs[locked:])
             sl = slice(locked, ne)
             C[:, sl] = C[:, sl][:, order]
             Lam[sl] = Lam[sl][order]

@@ -211,6 +211,51 @@ def check_degree_opt(oc):
     assert checked == 4
 
 
+def check_degree_order(oc):
+    """Alg. 1's sort of the active columns by degree (R8: stable, ascending).
+    Brute force over every pair of output positions: a permutation, with
+    degrees non-decreasing and equal degrees in their input order.  Then in a
+    solve: every filter call from the second iteration on sees non-decreasing
+    degrees, and columns of equal degree in ascending Rayleigh quotient (the
+    Ritz order they left Rayleigh-Ritz and locking in)."""
+    rng = np.random.default_rng(8)
+    for n in (1, 2, 7, 40):
+        degs = rng.choice(np.arange(2, 38, 2), n)
+        p = [int(x) for x in oc.degree_order(degs)]
+        assert sorted(p) == list(range(n)), p
+        for a in range(n):
+            for b in range(a + 1, n):
+                assert degs[p[a]] < degs[p[b]] or (degs[p[a]] == degs[p[b]] and p[a] < p[b]), (degs, p)
+
+    N, nev, nex = 150, 12, 6
+    lam = np.concatenate([np.linspace(-1.0, -0.9, 20), np.linspace(-0.5, 4.0, N - 20)])
+    Q, _ = np.linalg.qr(synth.complex_gaussian(np.random.default_rng(81), (N, N)))
+    A = (Q * lam) @ Q.conj().T
+    A = 0.5 * (A + A.conj().T)
+    calls = []
+    real_filter = oc.chebyshev_filter
+
+    def spy(A_, V, degs, c, e, mu1):
+        rq = np.real(np.sum(V.conj() * (A_ @ V), axis=0)) / np.real(np.sum(V.conj() * V, axis=0))
+        calls.append((np.array(degs), rq))
+        return real_filter(A_, V, degs, c, e, mu1)
+
+    oc.chebyshev_filter = spy
+    try:
+        r = oc.chase(A, oc.Params(nev=nev, nex=nex, deg=8), rng_seed=3)
+    finally:
+        oc.chebyshev_filter = real_filter
+    assert r.converged and len(calls) >= 3
+    ties = 0
+    for degs, rq in calls[1:]:
+        assert np.all(np.diff(degs) >= 0), degs
+        for j in range(degs.shape[0] - 1):
+            if degs[j] == degs[j + 1]:
+                ties += 1
+                assert rq[j] <= rq[j + 1] + 1e-12 * np.max(np.abs(lam)), (degs, rq)
+    assert ties > 0
+
+
 def check_lock_order(oc):
     """Locking in Alg. 2: among the first n_lockable active pairs, those
     with resd <= tol move to the front in their order; the rest keep their

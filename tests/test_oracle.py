@@ -20,6 +20,7 @@ PINS = [
     pins.check_condest_golden,
     pins.check_condest_overflow,
     pins.check_degree_opt,
+    pins.check_degree_order,
     pins.check_lock_order,
     pins.check_qr_selection,
     pins.check_shift_formula,
@@ -310,6 +311,19 @@ def _degree_no_margin(resd, Lam, c, e, tol_abs, max_deg, deg_extra):
     return oc.degree_opt(resd, Lam, c, e, tol_abs, max_deg, 0)
 
 
+def _degree_order_descending(degs):
+    return np.argsort(-np.asarray(degs), kind="stable")
+
+
+def _degree_order_ties_reversed(degs):
+    degs = np.asarray(degs)
+    return np.lexsort((-np.arange(degs.shape[0]), degs))
+
+
+def _degree_order_none(degs):
+    return np.arange(np.asarray(degs).shape[0])
+
+
 def _lock_past_nev(resd_active, n_lockable, tol_abs):
     return oc.lock_order(resd_active, resd_active.shape[0], tol_abs)
 
@@ -367,6 +381,10 @@ MUTANTS = [
     ("degree rounded down", dict(degree_opt=_degree_floor), [pins.check_degree_opt]),
     ("degree without margin", dict(degree_opt=_degree_no_margin), [pins.check_degree_opt]),
     ("locking past nev", dict(lock_order=_lock_past_nev), [pins.check_lock_order]),
+    ("degree sort descending", dict(degree_order=_degree_order_descending), [pins.check_degree_order]),
+    ("degree sort with ties reversed", dict(degree_order=_degree_order_ties_reversed),
+     [pins.check_degree_order]),
+    ("no degree sort", dict(degree_order=_degree_order_none), [pins.check_degree_order]),
     ("DoS count off by one", dict(lanczos_bounds=_dos_next_count), [pins.check_dos_closed_form]),
     ("DoS weights from the last component", dict(lanczos_bounds=_dos_last_component),
      [pins.check_dos_closed_form]),
