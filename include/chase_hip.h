@@ -287,10 +287,11 @@ int chase_caqr_real(double* V, int64_t ldv, int64_t N, int64_t n, double cond, i
  *   A (device) N x N complex128, read only; V (device) N x n complex128,
  *   in/out (widened back to complex128 as each column reaches its degree);
  *   degs (host) n even degrees >= 2, ascending; *matvecs (host) sum_j d_j.
+ *   n = 0 is a no-op (0 MatVecs, nothing allocated), as for chase_filter.
  * The copies of H (8 N^2 bytes for FP32, four bfloat16 planes for BF16x3)
  * and the complex64 blocks are allocated per call (2 on failure).
  * -1 null/unaligned A, -2 lda < N, -3 null/unaligned V, -4 ldv < N,
- * -5 N < 2, -6 n outside [1, N], -7 bad degrees, -9 e <= 0, -11 precision. */
+ * -5 N < 2, -6 n outside [0, N], -7 bad degrees, -9 e <= 0, -11 precision. */
 int chase_filter_lowp(const void* A, int64_t lda, void* V, int64_t ldv, int64_t N, int64_t n,
                       const int32_t* degs, double c, double e, double mu_1, int32_t precision,
                       int64_t* matvecs, chase_stream_t stream);

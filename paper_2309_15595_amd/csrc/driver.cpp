@@ -2239,12 +2239,16 @@ int chase_filter_lowp(const void* A, int64_t lda, void* V, int64_t ldv, int64_t 
   if (!V || !aligned16(V)) return -3;
   if (ldv < N) return -4;
   if (N < 2) return -5;
-  if (n < 1 || n > N) return -6;
-  if (!degs) return -7;
+  if (n < 0 || n > N) return -6;
+  if (n > 0 && !degs) return -7;
   for (int64_t j = 0; j < n; ++j)
     if (degs[j] < 2 || degs[j] % 2 || (j > 0 && degs[j] < degs[j - 1])) return -7;
   if (!(e > 0)) return -9;
   if (precision != CHASE_FP32_MIXED && precision != CHASE_BF16X3_MIXED) return -11;
+  if (n == 0) {  // no columns: nothing to filter, nothing allocated
+    if (matvecs) *matvecs = 0;
+    return kOk;
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool bf16 = precision == CHASE_BF16X3_MIXED;
   Workspace w;

@@ -119,6 +119,28 @@ def test_filter_leading_dimension(L):
     assert np.max(np.abs(got[:N] - ref)) <= 1e-11 * np.max(np.abs(ref))
 
 
+def test_filter_empty_block_is_a_no_op(L):
+    """No active columns (n = 0): the FP64, FP32 and BF16x3 filters and the
+    allocation-free one return 0 MatVecs and leave the block's memory as it
+    was, as the oracle's filter does for an empty block."""
+    N = 96
+    rng = np.random.default_rng(96)
+    A = synth.hermitian_from_spectrum(np.linspace(-1.0, 2.0, N), "gaussian", seed=96)
+    V = synth.complex_gaussian(rng, (N, 3))
+    out, mv_ref = oc.chebyshev_filter(A, V[:, :0], np.array([], dtype=np.int64), 1.1, 0.9, -0.999)
+    assert mv_ref == 0 and out.shape == (N, 0)
+    Ad, Vd = cm(A), cm(V)
+    Wd = cm(2.0 * V)
+    before_v, before_w = un(Vd), un(Wd)
+    c, e, mu1 = 1.1, 0.9, -0.999
+    assert L.chase_filter(L.dptr(Ad), N, L.dptr(Vd), N, L.dptr(Wd), N, N, 0, [], c, e, mu1, sp()) == 0
+    assert L.chase_filter_noalloc(L.dptr(Ad), N, L.dptr(Vd), N, L.dptr(Wd), N, N, 0, [], c, e, mu1, sp()) == 0
+    for code in (L.CHASE_FP32_MIXED, L.CHASE_BF16X3_MIXED):
+        assert L.chase_filter_lowp(L.dptr(Ad), N, L.dptr(Vd), N, N, 0, [], c, e, mu1, code, sp()) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(un(Vd), before_v) and np.array_equal(un(Wd), before_w)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_filter_lowp_matches_oracle(L, prec):
     """The FP32 and BF16x3 filter steps of the mixed solve against the FP64
