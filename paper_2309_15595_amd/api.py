@@ -165,14 +165,36 @@ def eigsh(A: torch.Tensor, nev: int, nex: int, *, deg: int = 20, tol: float = 1e
           opt: bool = True, max_deg: int = 36, max_iter: int = 25, V0=None, starts=None,
           precision: str = "fp64", seed: int = 2309, return_raw: bool = False):
     """nev lowest eigenpairs of the Hermitian (N, N) complex128 CUDA tensor A,
-    or of the real symmetric float64 one (then the real path, real vectors).
+    of the real symmetric float64 one (then the real path, real vectors), or
+    of a complex64 one (H used in place: FP32 filter and H Q products, the
+    rest in FP64; residuals bottom out near sqrt(N) 2^-24 ||H||, so pass a
+    tol such as 1e-5).
 
     Returns (evals (nev,) float64 tensor, evecs (N, nev) tensor of A's dtype,
     SolveInfo).  V0 (N, nev+nex) optional initial block, starts (N, r)
-    optional Lanczos start vectors.
+    optional Lanczos start vectors, both of A's dtype.
     """
     N = A.shape[0]
     ne = nev + nex
+    if A.dtype == torch.complex64:
+        if precision != "fp64":
+            raise ValueError("the complex64 path fixes its own precisions (FP32 products, FP64 elsewhere)")
+        _check_dev(A, (N, N), torch.complex64)
+        with Solver(N, nev, nex, dtype=torch.complex64, deg=deg, tol=tol, opt=int(opt), max_deg=max_deg,
+                    max_iter=max_iter, seed=seed) as s:
+            # as for complex128: A's memory read column-major is conj(A)
+            if V0 is not None:
+                Vt = V0.conj().transpose(0, 1).contiguous()
+            else:
+                Vt = torch.empty((ne, N), dtype=torch.complex64, device=A.device)
+            st = None if starts is None else starts.conj().transpose(0, 1).contiguous()
+            ritz, resid, info = s.solve_colmajor(A, Vt, use_v0=V0 is not None, starts_cm=st)
+        info.stats["resid"] = resid
+        evals = torch.from_numpy(ritz).to(A.device)
+        evecs = Vt[:nev].transpose(0, 1).conj()
+        if return_raw:
+            return evals, evecs, info, Vt
+        return evals, evecs, info
     if A.dtype == torch.float64:
         if precision != "fp64":
             raise ValueError("the real symmetric path is FP64 only")

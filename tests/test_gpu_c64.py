@@ -129,3 +129,25 @@ def test_c64_tiny_orders(L, N, nev, nex):
     ritz, resid, X, info = solve_c64(p)
     assert info.converged, info.stats
     assert np.max(np.abs(ritz - p.lam[: nev])) <= 1e-6 * p.norm2
+
+
+def test_c64_eigsh_torch_layout(L):
+    """eigsh on a row-major complex64 torch tensor: A's (not conj(A)'s)
+    vectors, eigenvalues within 1e-6 ||H|| of the prescribed spectrum, and
+    the same eigenvalues as the column-major Solver call on the same data."""
+    from paper_2309_15595_amd.api import eigsh
+    p = synth.make_problem(256, 10, 6, spectrum="uniform", seed=44)
+    A32 = p.A.astype(np.complex64)
+    A = torch.from_numpy(A32).cuda()
+    evals, evecs, info = eigsh(A, p.nev, p.nex, tol=TOL, V0=torch.from_numpy(p.V0.astype(np.complex64)).cuda(),
+                               starts=torch.from_numpy(p.starts.astype(np.complex64)).cuda())
+    assert info.converged, info.stats
+    assert evecs.dtype == torch.complex64
+    X = evecs.cpu().numpy().astype(np.complex128)
+    ev = evals.cpu().numpy()
+    A64 = A32.astype(np.complex128)
+    assert np.max(np.abs(ev - p.lam[: p.nev])) <= 1e-6 * p.norm2
+    assert np.max(np.linalg.norm(A64 @ X - X * ev, axis=0)) <= 4 * TOL * p.norm2
+    assert np.linalg.norm(X.conj().T @ X - np.eye(p.nev), 2) <= 1e-5
+    with pytest.raises(ValueError):
+        eigsh(A, p.nev, p.nex, precision="bf16x3")
