@@ -119,6 +119,59 @@ def test_filter_leading_dimension(L):
     assert np.max(np.abs(got[:N] - ref)) <= 1e-11 * np.max(np.abs(ref))
 
 
+def test_filter_padded_leading_dimensions(L):
+    """lda, ldv, ldw above N and odd (N = 517: a ragged row panel; 37 columns
+    of mixed degrees: a ragged column tile): the same columns as the oracle,
+    with NaN in H's padding rows (never read) and markers in the padding rows
+    of V and W (never written)."""
+    N, n = 517, 37
+    lda, ldv, ldw = N + 3, N + 5, N + 1
+    rng = np.random.default_rng(517)
+    lam = np.sort(rng.uniform(-1.0, 2.0, N))
+    A = synth.hermitian_from_spectrum(lam, "gaussian", seed=517)
+    degs = np.sort(rng.choice(np.arange(2, 38, 2), n))
+    V = synth.complex_gaussian(rng, (N, n))
+    c, e, mu1 = 1.1, 0.9, lam[0] + 1e-3
+    ref, mv_ref = oc.chebyshev_filter(A, V, degs, c, e, mu1)
+    Abig = np.full((lda, N), np.nan + 1j * np.nan)
+    Abig[:N] = A
+    Vbig = np.full((ldv, n), 7.0 + 7.0j)
+    Vbig[:N] = V
+    Wbig = np.full((ldw, n), -3.0 + 0.0j)
+    Ad, Vd, Wd = cm(Abig), cm(Vbig), cm(Wbig)
+    mv = L.chase_filter(L.dptr(Ad), lda, L.dptr(Vd), ldv, L.dptr(Wd), ldw, N, n, degs, c, e, mu1, sp())
+    assert mv == mv_ref
+    got_v, got_w = un(Vd), un(Wd)
+    err = np.linalg.norm(got_v[:N] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= 1e-11, err.max()
+    assert np.all(got_v[N:] == 7.0 + 7.0j) and np.all(got_w[N:] == -3.0)
+
+
+def test_solve_padded_leading_dimensions(L):
+    """chase_solve with an odd lda and ldv above N, through the C ABI: NaN in
+    H's padding rows, a marker in the block's; the same pairs as the packed
+    layout and the prescribed spectrum."""
+    p = synth.make_problem(300, 12, 6, spectrum="dft", seed=33)
+    lda, ldv = p.N + 3, p.N + 7
+    Abig = np.full((lda, p.N), np.nan + 1j * np.nan)
+    Abig[: p.N] = p.A
+    Vbig = np.full((ldv, p.ne), 5.0 - 1.0j)
+    Vbig[: p.N] = p.V0
+    prm = L.default_params(nev=p.nev, nex=p.nex)
+    h = L.chase_create(p.N, prm)
+    try:
+        Ad, Vd, Sd = cm(Abig), cm(Vbig), cm(p.starts)
+        ritz, resid, st = L.chase_solve(h, L.dptr(Ad), lda, L.dptr(Vd), ldv, 1, L.dptr(Sd), p.N, 4, p.nev, sp())
+    finally:
+        L.chase_destroy(h)
+    assert st.status == 0
+    got = un(Vd)
+    assert np.all(got[p.N:] == 5.0 - 1.0j)
+    ref_ritz, _, _, _ = solve_gpu(p)
+    assert np.max(np.abs(np.array(ritz) - ref_ritz)) <= 1e-12 * p.norm2
+    check_solution(p, np.array(ritz), np.array(resid), got[: p.N, : p.nev])
+
+
 def test_filter_empty_block_is_a_no_op(L):
     """No active columns (n = 0): the FP64, FP32 and BF16x3 filters and the
     allocation-free one return 0 MatVecs and leave the block's memory as it
