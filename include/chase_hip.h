@@ -143,7 +143,12 @@ int chase_workspace_bytes(int64_t N, const chase_params_t* p, int32_t variant, i
  *          4 from params.seed
  *   ritzv, resid (host) nev doubles each: eigenvalues ascending, residual
  *          norms ||H x - lambda x||_2
- *   stats  (host, nullable) */
+ *   stats  (host, nullable)
+ * With CHASE_LOG=1 in the environment (read once per process) every solve
+ * (all variants, and each problem of chase_solve_batched) prints one line per
+ * outer iteration on stderr: the locked count, CondEst and the QR variant it
+ * chose, the active residuals' range against tol, the filter degrees' range
+ * and the eigensolve's Jacobi sweeps. */
 int chase_solve(chase_handle_t h, const void* A, int64_t lda, void* V, int64_t ldv, int32_t use_v0,
                 const void* starts, int64_t ld_starts, int32_t nstarts, double* ritzv, double* resid,
                 chase_stats_t* stats, chase_stream_t stream);  /* -1: null, real or complex64 handle */

@@ -24,6 +24,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <complex>
 #include <functional>
 #include <cstring>
@@ -1042,6 +1044,16 @@ static int kappa_of_block(Workspace& w, const z64* X, int64_t ldx, int64_t n, bo
 
 // State of one problem's ChASE loop (Alg. 2).  The single solve and the
 // batched solve drive the same steps; only the filter launch differs.
+// CHASE_LOG=1 in the environment (read once): one line per outer iteration
+// on stderr.
+static bool chase_log_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("CHASE_LOG");
+    return v != nullptr && v[0] != '\0' && v[0] != '0';
+  }();
+  return on;
+}
+
 struct ProblemState {
   Workspace* w = nullptr;
   chase_params_t P{};
@@ -1304,11 +1316,19 @@ struct ProblemState {
   // The part of post_filter up to the Rayleigh-Ritz projection (the n_a x n_a
   // quotient in w->G), and the part after its eigensolve.
   double acc0[3] = {0, 0, 0};  // phase timers when the iteration's trace record began
+  double log_cond = 0;          // this iteration's CondEst and filter degree range (CHASE_LOG)
+  int log_dmin = 0, log_dmax = 0;
   int post_filter_a(hipStream_t s) {
     int st = kOk;
     std::vector<double> Lam_est = Lam;
     if (it == 1) std::fill(Lam_est.begin(), Lam_est.end(), mu1_cur);
     const double cond = cond_est(Lam_est.data(), c, e, degs.data(), ne, locked);
+    log_cond = cond;
+    log_dmin = log_dmax = 0;
+    if (na() > 0) {
+      log_dmin = *std::min_element(degs.begin() + locked, degs.end());
+      log_dmax = *std::max_element(degs.begin() + locked, degs.end());
+    }
     acc0[0] = t_f.acc;
     acc0[1] = t_qr.acc;
     acc0[2] = t_rr.acc;
@@ -1414,6 +1434,19 @@ struct ProblemState {
         if ((st = apply_perm(*w, V + (int64_t)locked * ldv, ldv, order, true, locked, s))) return st;
         permute_state(order);
       }
+    }
+    if (chase_log_enabled()) {
+      static const char* const kQr[4] = {"CholQR", "CholQR2", "sCholQR2", "HHQR"};
+      double rmin = INFINITY, rmax = 0.0;
+      for (int j = locked; j < ne; ++j) {
+        rmin = std::min(rmin, resd[j]);
+        rmax = std::max(rmax, resd[j]);
+      }
+      std::fprintf(stderr,
+                   "[chase] N=%lld nev=%d it %d: locked %d (+%d) of %d, CondEst %.3g -> %s, resid %.2e..%.2e "
+                   "(tol %.2e), degrees %d..%d, Jacobi sweeps %d\n",
+                   (long long)N, nev, it, locked + n_new, n_new, nev, log_cond,
+                   kQr[rec.qr_variant & 3], rmin, rmax, tol_abs, log_dmin, log_dmax, w->jac_sweeps);
     }
     locked += n_new;
     ++it;

@@ -790,3 +790,34 @@ def test_autograd_finite_difference_200(L):
     fd = (Lp - Lm) / (2 * h)
     # solver error <= tol ||A|| per eigenvalue -> FD error ~ 1e-10 ||A|| / h
     assert abs(fd - an) <= 1e-4 * max(1.0, abs(an)), (fd, an)
+
+
+def test_chase_log_prints_one_line_per_iteration(L):
+    """CHASE_LOG=1 (read once per process, so the solve runs in a child):
+    one line per outer iteration on stderr, its locked counts reaching nev
+    and its QR variants those the statistics count."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import json, sys, torch\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "import synth\n"
+        "from paper_2309_15595_amd.api import Solver, colmajor\n"
+        "p = synth.make_problem(300, 12, 6, seed=12)\n"
+        "with Solver(p.N, p.nev, p.nex) as s:\n"
+        "    ritz, resid, info = s.solve_colmajor(colmajor(p.A), colmajor(p.V0), True, colmajor(p.starts))\n"
+        "print(json.dumps({'it': info.stats['iterations'], 'qr': list(info.stats['qr_count']),"
+        " 'conv': bool(info.converged)}))\n")
+    env = dict(os.environ, CHASE_LOG="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    lines = [ln for ln in out.stderr.splitlines() if ln.startswith("[chase] N=300 nev=12 it ")]
+    assert res["conv"] and len(lines) == res["it"], (res, lines)
+    names = ["CholQR", "CholQR2", "sCholQR2", "HHQR"]
+    counts = [sum(f"-> {n}," in ln for ln in lines) for n in names]
+    assert counts == res["qr"], (counts, res["qr"])
+    assert lines[-1].split("locked ")[1].startswith("12 ")
